@@ -1,0 +1,186 @@
+/*
+ * cbvh.h -- compressed bounding volume hierarchies for collision detection
+ * and proximity queries between rigid triangle meshes, on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method follows Tan, Weller and Zachmann, "Compressed Bounding Volume
+ * Hierarchies for Collision Detection & Proximity Query":
+ *   - BV descriptors (axis-aligned boxes or 18-DOPs, Table I) are quantized
+ *     to 8- or 16-bit integer codes relative to the decoded parent BV, i.e.
+ *     each node is predicted from the chain of BVs above it and the code is
+ *     the corrector (abstract; section III.B "predictors based on the delta
+ *     to the parent nodes"; conclusion);
+ *   - the BVH is clustered into treelets, contiguous groups of sibling
+ *     groups whose top group stores absolute bounds, so any node can be
+ *     decoded from its treelet without the whole ancestor chain (abstract,
+ *     section III.B "cluster BVHs into a smaller parts");
+ *   - two BVHs are traversed simultaneously (Algorithm 1) for a collision
+ *     answer per pose, all colliding triangle pairs, or the minimum
+ *     separation distance (Introduction: collision detection and proximity
+ *     query between a sampled configuration and obstacles).
+ *
+ * Conventions for every function below:
+ *   - Functions return cbvh_status and never abort or throw across the ABI;
+ *     cbvh_last_error() gives a thread-local message for the last failure.
+ *   - Host models (cbvh_model) are owned by the library, immutable after
+ *     build/load, and safe to share between threads.
+ *   - All device memory is owned by the caller (e.g. torch tensors); the
+ *     query functions allocate no device memory of their own.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Device work is enqueued asynchronously on it; argument and format
+ *     errors are reported synchronously, before anything is enqueued.
+ *   - A pose is float32 [3][4] row-major [R | t]; a point x of model A is
+ *     placed in model B's frame as R x + t.  R should be a rotation.
+ *   - Triangle indices in outputs are the caller's input indices.
+ */
+#ifndef CBVH_H
+#define CBVH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CBVH_OK = 0,
+    CBVH_E_INVALID = 1,     /* bad argument (NULL pointer, size, parameter, mesh) */
+    CBVH_E_NOMEM = 2,       /* host allocation failed */
+    CBVH_E_DEVICE = 3,      /* a HIP call failed (message has the HIP error string) */
+    CBVH_E_CAPACITY = 4,    /* a caller-provided buffer or workspace is too small */
+    CBVH_E_UNSUPPORTED = 5, /* valid but unsupported combination (e.g. models of different BV type) */
+    CBVH_E_FORMAT = 6       /* a serialized model failed validation */
+} cbvh_status;
+
+typedef enum { CBVH_AABB = 0, CBVH_DOP18 = 1 } cbvh_bv;
+
+/* Build parameters.  Table I of the paper lists the descriptor sizes
+ * (AABB 6 floats, k-DOP k floats); `bits` selects the quantized width. */
+typedef struct {
+    uint32_t size;          /* = sizeof(cbvh_build_params) */
+    uint32_t bv;            /* CBVH_AABB (3 slabs) or CBVH_DOP18 (9 slabs) */
+    uint32_t branching;     /* children per inner node: 2, 4 or 8 */
+    uint32_t leaf_size;     /* triangles per leaf: 1..8 */
+    uint32_t bits;          /* 0 = FP32 descriptors (uncompressed), 8 or 16 = quantized codes */
+    uint32_t treelet_bytes; /* byte budget of one treelet; 0 = default (8192); >= 256 otherwise */
+} cbvh_build_params;
+
+typedef struct cbvh_model cbvh_model;
+
+typedef struct {
+    uint32_t bv, slabs, bits, branching, leaf_size;
+    uint32_t n_nodes, n_inner, n_leaves, n_tris, n_abs, n_treelets, depth;
+    uint64_t blob_bytes;       /* whole serialized model (= device bytes) */
+    uint64_t descriptor_bytes; /* bytes of BV descriptors: codes + absolute bounds */
+    uint64_t topology_bytes;   /* 4 bytes per node */
+    uint64_t triangle_bytes;   /* 36 bytes per triangle */
+} cbvh_model_info;
+
+/* Build a compressed BVH from a triangle mesh (host only).
+ * V: nv x 3 float32 vertex coordinates; T: nt x 3 uint32 vertex indices.
+ * Both are borrowed for the duration of the call and copied.  Fails with
+ * CBVH_E_INVALID for nt == 0, nt >= 2^27, an index >= nv, or a
+ * non-finite / |x| >= 2^60 coordinate.  Topology: median splits, log2(BF)
+ * binary rounds per node on the longest axis of the centroid bounds, leaves
+ * kept full; identical for every `bv` and `bits` so compressed and
+ * uncompressed models share it. */
+cbvh_status cbvh_build(const float *V, uint32_t nv, const uint32_t *T, uint32_t nt,
+                       const cbvh_build_params *params, cbvh_model **out);
+
+/* Release a host model (NULL is ignored).  Device copies are not affected. */
+void cbvh_free(cbvh_model *m);
+
+/* Borrowed view of the serialized model: the exact bytes that cbvh_upload
+ * copies to the device.  Valid until cbvh_free(m). */
+cbvh_status cbvh_blob(const cbvh_model *m, const void **bytes, size_t *n);
+
+/* Re-create a model from serialized bytes (copied); validates every offset,
+ * index and range so that device traversal of the result stays in bounds.
+ * CBVH_E_FORMAT on any inconsistency. */
+cbvh_status cbvh_load(const void *bytes, size_t n, cbvh_model **out);
+
+cbvh_status cbvh_info(const cbvh_model *m, cbvh_model_info *out);
+
+/* Device bytes needed by cbvh_upload (the blob size). */
+size_t cbvh_device_bytes(const cbvh_model *m);
+
+/* Copy the model into caller-owned device memory `dev` (>= cbvh_device_bytes,
+ * 256-byte aligned), asynchronously on `stream`.  The host model must stay
+ * alive until the copy has completed. */
+cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *stream);
+
+/* Query flags */
+#define CBVH_EARLY_EXIT 0x1u /* collide: stop a pose at its first colliding triangle pair */
+#define CBVH_PAIRS 0x2u      /* collide: report every colliding triangle pair */
+#define CBVH_NO_FALLBACK 0x4u /* do not re-run stack-overflowing poses with the large global stack */
+
+/* Per-pose status bytes written by the queries */
+#define CBVH_POSE_OK 0u
+#define CBVH_POSE_STACK_OVERFLOW 1u /* traversal stack exhausted even in the fallback; results invalid */
+#define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
+
+/* Workspace bytes (device, caller-owned, 256-byte aligned) for a query on
+ * models a and b with n poses. */
+size_t cbvh_workspace_bytes(const cbvh_model *a, const cbvh_model *b, uint32_t n_poses, uint32_t flags,
+                            uint32_t pair_capacity);
+
+/* Collision detection for a batch of poses (Algorithm 1; leaf test is the
+ * closed triangle-triangle intersection, touching counts).
+ *   a, a_dev: moving model and its uploaded copy; b, b_dev: fixed model.
+ *   poses:    device float32 [n][3][4].
+ *   hit:      device uint8 [n]: 1 if any triangle pair intersects.
+ *   With CBVH_PAIRS: pairs = device uint32 [pair_capacity][3] receives
+ *   (pose, triA, triB) sorted by pose, then triA, then triB; pair_offsets =
+ *   device uint32 [n+1] receives each pose's start (pair_offsets[n] = number
+ *   stored).  CBVH_PAIRS and CBVH_EARLY_EXIT are mutually exclusive.
+ *   pose_status: device uint8 [n] (CBVH_POSE_*).
+ *   workspace: device, >= cbvh_workspace_bytes(a, b, n, flags, pair_capacity).
+ * Models must have the same BV type.  n == 0 is a no-op. */
+cbvh_status cbvh_collide(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                         const float *poses, uint32_t n, uint32_t flags, uint8_t *hit, uint32_t *pairs,
+                         uint32_t pair_capacity, uint32_t *pair_offsets, uint8_t *pose_status, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Minimum separation distance per pose (proximity query; 0 if the meshes
+ * intersect).  dist: device float32 [n].  Leaf distances run in FP32 and
+ * every leaf pair whose FP32 distance could be the minimum is re-evaluated
+ * in FP64; the result is the FP64 minimum rounded to float32. */
+cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                          const float *poses, uint32_t n, uint32_t flags, float *dist, uint8_t *pose_status,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* Decode every node's bounds on the device: out = device float32
+ * [n_nodes][2*slabs] as (lo, hi) per slab.  Parity tool for the decoder. */
+cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, void *stream);
+
+/* Counters of the last query that used this workspace.  Synchronizes
+ * `stream` and copies them to the host. */
+typedef struct {
+    uint64_t bv_tests;       /* BV-pair overlap / lower-bound evaluations (Algorithm 1 "intersect") */
+    uint64_t tri_tests;      /* triangle-pair tests (FP32) */
+    uint64_t tri_fp64;       /* triangle-pair tests re-decided or refined in FP64 */
+    uint64_t expansions;     /* node-pair expansions (children fetched and decoded) */
+    uint64_t node_bytes;     /* descriptor + topology bytes the expansions fetched */
+    uint64_t tri_bytes;      /* triangle bytes the leaf tests fetched */
+    uint64_t fallback_poses; /* poses re-run on the large global-memory stack */
+    uint64_t max_entries;    /* deepest traversal stack seen (entries) */
+    uint64_t max_records;    /* most decoded-BV records live at once */
+    uint64_t reserved[7];
+} cbvh_stats_t;
+
+cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream);
+
+/* Test hook: cap the fast (LDS) traversal stack at `entries` entries and
+ * `records` decoded-BV records (0 restores the defaults), so tests can force
+ * the overflow path from the host.  Affects subsequent queries of this
+ * process. */
+cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records);
+
+/* Thread-local message describing the last failure (never NULL). */
+const char *cbvh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBVH_H */

@@ -536,9 +536,20 @@ static inline int bv_overlap(const pose_t *P, const onode_t *a, const onode_t *b
     return box_gap(P, a, b) <= dilate + box_slack(P, a, b);
 }
 
+/* distance lower bound of two boxes: the larger of the largest axis gap and
+ * the gap between their circumscribed spheres (both are lower bounds) */
 static inline double bv_lower_bound(const pose_t *P, const onode_t *a, const onode_t *b)
 {
-    double g = box_gap(P, a, b) - box_slack(P, a, b);
+    double ca[3], cb[3], c[3], d[3], ra = 0, rb = 0;
+    for (int k = 0; k < 3; k++) {
+        ca[k] = 0.5 * (a->lo[k] + a->hi[k]); cb[k] = 0.5 * (b->lo[k] + b->hi[k]);
+        ra += 0.25 * (a->hi[k] - a->lo[k]) * (a->hi[k] - a->lo[k]);
+        rb += 0.25 * (b->hi[k] - b->lo[k]) * (b->hi[k] - b->lo[k]);
+    }
+    pose_apply(P, ca, c);
+    vsub(c, cb, d);
+    double gs = sqrt(vnorm2(d)) - sqrt(ra) - sqrt(rb);
+    double g = dmax(box_gap(P, a, b), gs) - box_slack(P, a, b);
     return g > 0 ? g : 0.0;
 }
 

@@ -1,0 +1,340 @@
+// The C ABI of include/cbvh.h: argument validation, model lifetime, device
+// views of uploaded models, workspace carving and kernel dispatch.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <atomic>
+#include <new>
+#include <string>
+
+#include "../../include/cbvh.h"
+#include "format.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+cbvh_status fail(cbvh_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+cbvh_status fail_hip(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return CBVH_E_DEVICE;
+}
+
+std::atomic<uint32_t> g_limit_entries{0}, g_limit_records{0};
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
+{
+    const uint8_t *b = (const uint8_t *)dev;
+    const cbvh::BlobHeader &h = m->hdr;
+    cbvh::DevModel d;
+    d.topo = (const uint32_t *)(b + h.off_topo);
+    d.codes = b + h.off_codes;
+    d.absb = (const float *)(b + h.off_abs);
+    d.tris = (const float *)(b + h.off_tris);
+    d.perm = (const uint32_t *)(b + h.off_perm);
+    d.treelets = (const uint32_t *)(b + h.off_treelets);
+    d.n_nodes = h.n_nodes;
+    d.n_tris = h.n_tris;
+    d.n_treelets = h.n_treelets;
+    d.stride = h.code_stride;
+    d.bits = h.bits;
+    d.K = h.K;
+    d.leaf_size = h.leaf_size;
+    d.depth = h.depth;
+    d.max_abs = h.max_abs_coord;
+    return d;
+}
+
+cbvh::StackLimits current_limits(uint32_t K)
+{
+    cbvh::StackLimits l = cbvh::default_limits(K);
+    uint32_t e = g_limit_entries.load(), r = g_limit_records.load();
+    if (e) l.entries = e;
+    if (r) l.records = r;
+    return l;
+}
+
+// workspace carving: [header | fallback_list | fell_back | pair buffers | fallback stacks]
+struct WsPlan {
+    uint64_t hdr, fallback_list, fell_back, pair_raw, pair_cnt, pair_cursor, pair_keys, garena, total;
+    uint64_t garena_stride;
+};
+
+WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
+{
+    WsPlan p;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t r = o;
+        o = align_up(o + bytes, 256);
+        return r;
+    };
+    p.hdr = take(sizeof(cbvh::WsHeader));
+    p.fallback_list = take(4ull * n);
+    p.fell_back = take(n);
+    bool pairs = mode == cbvh::MODE_PAIRS;
+    p.pair_raw = take(pairs ? 16ull * pair_cap : 0);
+    p.pair_cnt = take(pairs ? 4ull * n : 0);
+    p.pair_cursor = take(pairs ? 4ull * n : 0);
+    p.pair_keys = take(pairs ? 8ull * pair_cap : 0);
+    p.garena_stride = align_up(cbvh::wave_state_bytes(K, mode, cbvh::fallback_limits(K)), 256);
+    p.garena = take(p.garena_stride * cbvh::fallback_waves());
+    p.total = o;
+    return p;
+}
+
+cbvh_status check_pair(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev)
+{
+    if (!a || !b) return fail(CBVH_E_INVALID, "model is NULL");
+    if (!a_dev || !b_dev) return fail(CBVH_E_INVALID, "device model pointer is NULL");
+    if (!aligned(a_dev, 256) || !aligned(b_dev, 256)) return fail(CBVH_E_INVALID, "device model not 256-byte aligned");
+    if (a->hdr.bv != b->hdr.bv) return fail(CBVH_E_UNSUPPORTED, "models have different BV types");
+    if (a->hdr.bits != b->hdr.bits) return fail(CBVH_E_UNSUPPORTED, "models have different code widths");
+    return CBVH_OK;
+}
+
+cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                      const float *poses, uint32_t n, int mode, uint32_t flags, uint8_t *hit, float *dist,
+                      uint32_t *pairs, uint32_t pair_cap, uint32_t *pair_offsets, uint8_t *status, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    cbvh_status st = check_pair(a, a_dev, b, b_dev);
+    if (st != CBVH_OK) return st;
+    if (n == 0) return CBVH_OK;
+    if (!poses || !status) return fail(CBVH_E_INVALID, "poses or pose_status is NULL");
+    if (mode == cbvh::MODE_DIST ? !dist : !hit) return fail(CBVH_E_INVALID, "output array is NULL");
+    if (!aligned(poses, 4)) return fail(CBVH_E_INVALID, "poses not 4-byte aligned");
+    if (mode == cbvh::MODE_PAIRS) {
+        if (!pairs || !pair_offsets) return fail(CBVH_E_INVALID, "pairs or pair_offsets is NULL");
+        if (pair_cap == 0) return fail(CBVH_E_INVALID, "pair_capacity is 0");
+        if (pair_cap > (1u << 30)) return fail(CBVH_E_INVALID, "pair_capacity too large");
+    }
+    if (n > (1u << 30)) return fail(CBVH_E_INVALID, "too many poses");
+    if (!ws) return fail(CBVH_E_INVALID, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(CBVH_E_INVALID, "workspace not 256-byte aligned");
+    WsPlan plan = plan_workspace(a->hdr.K, mode, n, pair_cap);
+    if (ws_bytes < plan.total) return fail(CBVH_E_CAPACITY, "workspace too small");
+    uint8_t *w = (uint8_t *)ws;
+    cbvh::QueryArgs q;
+    memset(&q, 0, sizeof q);
+    q.A = dev_view(a, a_dev);
+    q.B = dev_view(b, b_dev);
+    q.poses = poses;
+    q.n_poses = n;
+    q.mode = mode;
+    q.hit = hit;
+    q.dist = dist;
+    q.status = status;
+    q.pair_cap = pair_cap;
+    q.no_fallback = (flags & CBVH_NO_FALLBACK) ? 1u : 0u;
+    q.ws.hdr = (cbvh::WsHeader *)(w + plan.hdr);
+    q.ws.fallback_list = (uint32_t *)(w + plan.fallback_list);
+    q.ws.fell_back = w + plan.fell_back;
+    q.ws.pair_raw = (uint4 *)(w + plan.pair_raw);
+    q.ws.pair_cnt = (uint32_t *)(w + plan.pair_cnt);
+    q.ws.pair_cursor = (uint32_t *)(w + plan.pair_cursor);
+    q.ws.pair_keys = (unsigned long long *)(w + plan.pair_keys);
+    q.ws.garena = w + plan.garena;
+    q.ws.garena_stride = plan.garena_stride;
+    q.ws.garena_waves = cbvh::fallback_waves();
+    cbvh::StackLimits lim = current_limits(a->hdr.K);
+    hipError_t e = cbvh::launch_query(q, lim, (hipStream_t)stream, pairs, pair_offsets);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    return CBVH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cbvh_status cbvh_build(const float *V, uint32_t nv, const uint32_t *T, uint32_t nt, const cbvh_build_params *params,
+                       cbvh_model **out)
+{
+    try {
+        if (!out) return fail(CBVH_E_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!V || !T || !params) return fail(CBVH_E_INVALID, "V, T or params is NULL");
+        if (params->size != sizeof(cbvh_build_params)) return fail(CBVH_E_INVALID, "params.size mismatch");
+        if (nt == 0 || nt > cbvh::kIndexMask) return fail(CBVH_E_INVALID, "triangle count out of range");
+        if (nv == 0) return fail(CBVH_E_INVALID, "no vertices");
+        if (params->bv != CBVH_AABB && params->bv != CBVH_DOP18) return fail(CBVH_E_INVALID, "bad bv");
+        if (!(params->branching == 2 || params->branching == 4 || params->branching == 8))
+            return fail(CBVH_E_INVALID, "branching must be 2, 4 or 8");
+        if (params->leaf_size < 1 || params->leaf_size > cbvh::kMaxLeaf) return fail(CBVH_E_INVALID, "leaf_size must be 1..8");
+        if (!(params->bits == 0 || params->bits == 8 || params->bits == 16)) return fail(CBVH_E_INVALID, "bits must be 0, 8 or 16");
+        uint32_t tb = params->treelet_bytes ? params->treelet_bytes : 8192u;
+        if (tb < 256) return fail(CBVH_E_INVALID, "treelet_bytes must be 0 or >= 256");
+        cbvh::BuildParams p{params->bv, params->branching, params->leaf_size, params->bits, tb};
+        cbvh_model *m = new cbvh_model();
+        std::string msg = cbvh::build_model(V, nv, T, nt, p, m);
+        if (!msg.empty()) {
+            delete m;
+            return fail(CBVH_E_INVALID, msg);
+        }
+        *out = m;
+        return CBVH_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(CBVH_E_NOMEM, "out of host memory");
+    } catch (...) {
+        return fail(CBVH_E_INVALID, "unexpected error in build");
+    }
+}
+
+void cbvh_free(cbvh_model *m) { delete m; }
+
+cbvh_status cbvh_blob(const cbvh_model *m, const void **bytes, size_t *n)
+{
+    if (!m || !bytes || !n) return fail(CBVH_E_INVALID, "NULL argument");
+    *bytes = m->blob.data();
+    *n = m->blob.size();
+    return CBVH_OK;
+}
+
+cbvh_status cbvh_load(const void *bytes, size_t n, cbvh_model **out)
+{
+    try {
+        if (!out) return fail(CBVH_E_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!bytes) return fail(CBVH_E_INVALID, "bytes is NULL");
+        cbvh::BlobHeader h;
+        uint32_t ni = 0, nl = 0;
+        std::string msg = cbvh::validate_blob((const uint8_t *)bytes, n, &h, &ni, &nl);
+        if (!msg.empty()) return fail(CBVH_E_FORMAT, msg);
+        cbvh_model *m = new cbvh_model();
+        m->blob.assign((const uint8_t *)bytes, (const uint8_t *)bytes + n);
+        m->hdr = h;
+        m->n_inner = ni;
+        m->n_leaves = nl;
+        m->descriptor_bytes = (uint64_t)h.code_stride * h.n_nodes + 8ull * h.K * h.n_abs;
+        *out = m;
+        return CBVH_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(CBVH_E_NOMEM, "out of host memory");
+    } catch (...) {
+        return fail(CBVH_E_FORMAT, "unexpected error in load");
+    }
+}
+
+cbvh_status cbvh_info(const cbvh_model *m, cbvh_model_info *o)
+{
+    if (!m || !o) return fail(CBVH_E_INVALID, "NULL argument");
+    const cbvh::BlobHeader &h = m->hdr;
+    memset(o, 0, sizeof *o);
+    o->bv = h.bv;
+    o->slabs = h.K;
+    o->bits = h.bits;
+    o->branching = h.branching;
+    o->leaf_size = h.leaf_size;
+    o->n_nodes = h.n_nodes;
+    o->n_inner = m->n_inner;
+    o->n_leaves = m->n_leaves;
+    o->n_tris = h.n_tris;
+    o->n_abs = h.n_abs;
+    o->n_treelets = h.n_treelets;
+    o->depth = h.depth;
+    o->blob_bytes = m->blob.size();
+    o->descriptor_bytes = m->descriptor_bytes;
+    o->topology_bytes = 4ull * h.n_nodes;
+    o->triangle_bytes = 36ull * h.n_tris;
+    return CBVH_OK;
+}
+
+size_t cbvh_device_bytes(const cbvh_model *m) { return m ? m->blob.size() : 0; }
+
+cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *stream)
+{
+    if (!m || !dev) return fail(CBVH_E_INVALID, "NULL argument");
+    if (!aligned(dev, 256)) return fail(CBVH_E_INVALID, "device buffer not 256-byte aligned");
+    if (capacity < m->blob.size()) return fail(CBVH_E_CAPACITY, "device buffer too small");
+    hipError_t e = hipMemcpyAsync(dev, m->blob.data(), m->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync");
+    return CBVH_OK;
+}
+
+size_t cbvh_workspace_bytes(const cbvh_model *a, const cbvh_model *b, uint32_t n_poses, uint32_t flags,
+                            uint32_t pair_capacity)
+{
+    if (!a || !b) return 0;
+    int mode = (flags & CBVH_PAIRS) ? cbvh::MODE_PAIRS : cbvh::MODE_BOOL;
+    size_t x = plan_workspace(a->hdr.K, mode, n_poses, pair_capacity).total;
+    size_t y = plan_workspace(a->hdr.K, cbvh::MODE_DIST, n_poses, 0).total;
+    return x > y ? x : y;
+}
+
+cbvh_status cbvh_collide(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                         const float *poses, uint32_t n, uint32_t flags, uint8_t *hit, uint32_t *pairs,
+                         uint32_t pair_capacity, uint32_t *pair_offsets, uint8_t *pose_status, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    if ((flags & CBVH_PAIRS) && (flags & CBVH_EARLY_EXIT))
+        return fail(CBVH_E_INVALID, "CBVH_PAIRS and CBVH_EARLY_EXIT are exclusive");
+    if (flags & ~(CBVH_EARLY_EXIT | CBVH_PAIRS | CBVH_NO_FALLBACK)) return fail(CBVH_E_INVALID, "unknown flag");
+    int mode = (flags & CBVH_PAIRS) ? cbvh::MODE_PAIRS : cbvh::MODE_BOOL;
+    return run_query(a, a_dev, b, b_dev, poses, n, mode, flags, hit, nullptr, pairs, pair_capacity, pair_offsets,
+                     pose_status, workspace, workspace_bytes, stream);
+}
+
+cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                          const float *poses, uint32_t n, uint32_t flags, float *dist, uint8_t *pose_status,
+                          void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (flags & ~CBVH_NO_FALLBACK) return fail(CBVH_E_INVALID, "unknown flag");
+    return run_query(a, a_dev, b, b_dev, poses, n, cbvh::MODE_DIST, flags, nullptr, dist, nullptr, 0, nullptr,
+                     pose_status, workspace, workspace_bytes, stream);
+}
+
+cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, void *stream)
+{
+    if (!m || !m_dev || !out) return fail(CBVH_E_INVALID, "NULL argument");
+    if (!aligned(m_dev, 256)) return fail(CBVH_E_INVALID, "device model not 256-byte aligned");
+    if (!aligned(out, 4)) return fail(CBVH_E_INVALID, "out not 4-byte aligned");
+    hipError_t e = cbvh::launch_decode_all(dev_view(m, m_dev), out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "decode launch");
+    return CBVH_OK;
+}
+
+cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream)
+{
+    if (!workspace || !out) return fail(CBVH_E_INVALID, "NULL argument");
+    if (workspace_bytes < sizeof(cbvh::WsHeader)) return fail(CBVH_E_CAPACITY, "workspace too small");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    cbvh::WsHeader h;
+    e = hipMemcpy(&h, workspace, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    memset(out, 0, sizeof *out);
+    out->bv_tests = h.counters[cbvh::C_BV_TESTS];
+    out->tri_tests = h.counters[cbvh::C_TRI_TESTS];
+    out->tri_fp64 = h.counters[cbvh::C_TRI_FP64];
+    out->expansions = h.counters[cbvh::C_EXPANSIONS];
+    out->node_bytes = h.counters[cbvh::C_NODE_BYTES];
+    out->tri_bytes = h.counters[cbvh::C_TRI_BYTES];
+    out->fallback_poses = h.counters[cbvh::C_FALLBACK_POSES];
+    out->max_entries = h.counters[cbvh::C_MAX_ENTRIES];
+    out->max_records = h.counters[cbvh::C_MAX_RECORDS];
+    return CBVH_OK;
+}
+
+cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records)
+{
+    if (entries > 16384 || records > 8192) return fail(CBVH_E_INVALID, "limit too large");
+    if ((entries && entries < 2) || (records && records < 2)) return fail(CBVH_E_INVALID, "limit too small");
+    g_limit_entries.store(entries);
+    g_limit_records.store(records);
+    return CBVH_OK;
+}
+
+const char *cbvh_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

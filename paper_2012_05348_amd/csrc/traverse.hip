@@ -1,0 +1,1072 @@
+// Simultaneous traversal of two compressed BVHs on gfx950 (Algorithm 1 of
+// Tan, Weller, Zachmann, "Compressed Bounding Volume Hierarchies for
+// Collision Detection & Proximity Query"), one wavefront per pose.
+//
+// Per wave, in LDS (or, for the rare poses that overflow it, in a large
+// per-wave slice of global memory):
+//   records  decoded BVs (topology word + 2K float bounds) grouped in LIFO
+//            frames; a frame holds the children decoded by one node step
+//            and is the predictor for the next level's codes;
+//   entries  pending node pairs (A record, B record, frame id), LIFO;
+//   leafq    pending leaf pairs (two leaf topology words);
+//   ta       A's records of the current frame moved into B's frame.
+//
+// Node step: pop up to 4 entries whose child-pair tests fit in 64 lanes,
+// decode the children (one lane per child) into a new frame, transform A's
+// children with the pose's support-function coefficients, test every child
+// pair in its own lane (Algorithm 1's "a_i and b_j intersect", or a BV
+// distance lower bound), and compact the survivors with ballot + mbcnt into
+// the entry stack (inner pairs) or the leaf queue (leaf pairs).
+// Leaf step: up to 64 triangle pairs, one per lane (checkPrimitives).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "format.h"
+#include "geom.h"
+#include "kernels.h"
+
+namespace cbvh {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int EMAX = 4;                              // node-pair expansions per node step
+constexpr int TA_MAX = EMAX * (int)kMaxBranching;    // A records transformed per step
+constexpr int MAX_FRAMES = 64;
+constexpr uint32_t REC_BITS = 13;                    // entry: recA | recB << 13 | frame << 26
+constexpr uint32_t REC_MASK = (1u << REC_BITS) - 1u;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float unif(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ uint32_t lane_of(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+// a float not below the exact sum a + b
+__device__ __forceinline__ float add_up(float a, float b) { return nextafterf(a + b, INFINITY); }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane >= (uint32_t)o) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// per-wave state layout (identical on host and device)
+// ---------------------------------------------------------------------------
+struct Layout {
+    uint32_t coef, upidx, vtU, vtL, misc, frame_end, rtopo, rbnd, ta, ent, ent_lb, lq, lq_lb, scratch, total;
+};
+
+__host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
+{
+    Layout L;
+    uint32_t o = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t r = o;
+        o += (bytes + 15u) & ~15u;
+        return r;
+    };
+    L.coef = take(12 * K);
+    L.upidx = take(4 * K);
+    L.vtU = take(4 * K);
+    L.vtL = take(4 * K);
+    L.misc = take(16);
+    L.frame_end = take(4 * MAX_FRAMES);
+    L.rtopo = take(4 * lim.records);
+    L.rbnd = take(8 * K * lim.records);
+    L.ta = take(8 * K * TA_MAX);
+    L.ent = take(4 * lim.entries);
+    L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
+    L.lq = take(8 * lim.leafq);
+    L.lq_lb = mode == MODE_DIST ? take(4 * lim.leafq) : o;
+    L.scratch = take(4 * WAVE);
+    L.total = o;
+    return L;
+}
+
+// slab directions of the AABB (first 3) and the 18-DOP (all 9)
+__device__ __forceinline__ void slab_dir(int k, int v[3])
+{
+    // x, y, z, x+y, x+z, y+z, x-y, x-z, y-z
+    v[0] = (k == 0 || k == 3 || k == 4 || k == 6 || k == 7) ? 1 : 0;
+    v[1] = (k == 1 || k == 3 || k == 5) ? 1 : (k == 6 ? -1 : (k == 8 ? 1 : 0));
+    v[2] = (k == 2 || k == 4 || k == 5) ? 1 : ((k == 7 || k == 8) ? -1 : 0);
+}
+
+// u = sum alpha_m * sign_m * n(axis_m) with alpha >= 0 over three normals
+// of the fan of the 18 DOP normals {+-x, +-y, +-z, +-(x+-y), +-(x+-z),
+// +-(y+-z)}: the fan splits every octant into 4 triangular cones (a corner
+// cone per axis and the middle cone of the three diagonals).
+__device__ inline void dop18_cone(const double u[3], double alpha[3], int axis[3], int sgn[3])
+{
+    int sx = u[0] >= 0 ? 1 : -1, sy = u[1] >= 0 ? 1 : -1, sz = u[2] >= 0 ? 1 : -1;
+    double a = fabs(u[0]), b = fabs(u[1]), c = fabs(u[2]);
+    int gxy = sx * sy > 0 ? 3 : 6, gxz = sx * sz > 0 ? 4 : 7, gyz = sy * sz > 0 ? 5 : 8;
+    if (a >= b + c) {
+        alpha[0] = a - b - c; axis[0] = 0; sgn[0] = sx;
+        alpha[1] = b; axis[1] = gxy; sgn[1] = sx;
+        alpha[2] = c; axis[2] = gxz; sgn[2] = sx;
+    } else if (b >= a + c) {
+        alpha[0] = b - a - c; axis[0] = 1; sgn[0] = sy;
+        alpha[1] = a; axis[1] = gxy; sgn[1] = sx;
+        alpha[2] = c; axis[2] = gyz; sgn[2] = sy;
+    } else if (c >= a + b) {
+        alpha[0] = c - a - b; axis[0] = 2; sgn[0] = sz;
+        alpha[1] = a; axis[1] = gxz; sgn[1] = sx;
+        alpha[2] = b; axis[2] = gyz; sgn[2] = sy;
+    } else {
+        alpha[0] = 0.5 * (a + b - c); axis[0] = gxy; sgn[0] = sx;
+        alpha[1] = 0.5 * (a + c - b); axis[1] = gxz; sgn[1] = sx;
+        alpha[2] = 0.5 * (b + c - a); axis[2] = gyz; sgn[2] = sy;
+    }
+}
+
+// Per-pose setup (lanes 0..K-1, one slab axis v_k of B each).  A's node
+// polytope {x : lo_j <= n_j.x <= hi_j} moved by the pose projects onto v_k
+// inside [L_k, U_k] with
+//   U_k = v_k.t + sum_m alpha_m d_m   (support function bound: any alpha >= 0
+//   with sum alpha_m n_m = R^T v_k bounds the support of the polytope),
+// d_m the bound of generator m (hi for +n, -lo for -n).  Written as
+//   U_k = vtU_k + sum_m c_m b[up_m],  L_k = vtL_k + sum_m c_m b[up_m ^ 1]
+// with c_m = sign_m alpha_m and b the record's (lo, hi) array.  vtU/vtL
+// carry a pad covering every FP32 rounding of the bound's evaluation.
+template <int K>
+__device__ void pose_setup(const float *P, float maxA, float *coef, uint32_t *upidx, float *vtU, float *vtL,
+                           uint32_t lane)
+{
+    if (lane >= (uint32_t)K) return;
+    double R[3][3], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) R[i][j] = (double)P[4 * i + j];
+        t[i] = (double)P[4 * i + 3];
+    }
+    int v[3];
+    slab_dir((int)lane, v);
+    double u[3];
+    for (int j = 0; j < 3; j++) u[j] = R[0][j] * v[0] + R[1][j] * v[1] + R[2][j] * v[2];
+    double vt = t[0] * v[0] + t[1] * v[1] + t[2] * v[2];
+    double alpha[3];
+    int axis[3], sgn[3];
+    if (K == 3) {
+        for (int m = 0; m < 3; m++) {
+            alpha[m] = fabs(u[m]);
+            axis[m] = m;
+            sgn[m] = u[m] >= 0 ? 1 : -1;
+        }
+    } else {
+        dop18_cone(u, alpha, axis, sgn);
+    }
+    double asum = alpha[0] + alpha[1] + alpha[2];
+    double tmax = fmax(fabs(t[0]), fmax(fabs(t[1]), fabs(t[2])));
+    double vn1 = fabs((double)v[0]) + fabs((double)v[1]) + fabs((double)v[2]);
+    double SA = (K == 9 ? 2.0 : 1.0) * (double)maxA * (1.0 + 0x1p-20);
+    double pad = 8.0 * 0x1p-24 * (vn1 * tmax + asum * SA) + 0x1p-120;
+    uint32_t packed = 0;
+    for (int m = 0; m < 3; m++) {
+        coef[3 * lane + m] = (float)(sgn[m] * alpha[m]);
+        packed |= (uint32_t)(2 * axis[m] + (sgn[m] > 0 ? 1 : 0)) << (8 * m);
+    }
+    upidx[lane] = packed;
+    vtU[lane] = __double2float_ru(vt + pad);
+    vtL[lane] = __double2float_rd(vt - pad);
+}
+
+// Decode one node's 2K bounds (lo, hi per slab) from its parent's decoded
+// bounds: E = Ph - Pl, s = E * 2^-BITS (0 if E < 2^-100), lo = fma(ql, s, Pl),
+// hi = fma(-qh, s, Ph).  Absolute nodes (treelet tops) and uncompressed
+// models read FP32 bounds instead.
+template <int K, int BITS, typename ParentPtr>
+__device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, uint32_t topo, ParentPtr parent,
+                                            float out[2 * K])
+{
+    const uint8_t *code = M.codes + (size_t)node * M.stride;
+    if (BITS == 0) {
+        const float2 *c = (const float2 *)code;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            float2 w = c[k];
+            out[2 * k] = w.x;
+            out[2 * k + 1] = w.y;
+        }
+    } else if (topo_abs(topo)) {
+        uint32_t ai = *(const uint32_t *)code;
+        const float2 *c = (const float2 *)(M.absb + (size_t)ai * 2 * K);
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            float2 w = c[k];
+            out[2 * k] = w.x;
+            out[2 * k + 1] = w.y;
+        }
+    } else {
+        const float scale = 1.0f / (float)(1u << BITS);
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            uint32_t ql, qh;
+            if (BITS == 8) {
+                uint32_t w = *(const uint16_t *)(code + 2 * k);
+                ql = w & 0xFFu;
+                qh = w >> 8;
+            } else {
+                uint32_t w = *(const uint32_t *)(code + 4 * k);
+                ql = w & 0xFFFFu;
+                qh = w >> 16;
+            }
+            float Pl = parent[2 * k], Ph = parent[2 * k + 1];
+            float E = Ph - Pl;
+            float s = E >= 0x1p-100f ? E * scale : 0.0f;
+            out[2 * k] = __builtin_fmaf((float)ql, s, Pl);
+            out[2 * k + 1] = __builtin_fmaf(-(float)qh, s, Ph);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_tri(const float *tris, uint32_t i, V3<float> t[3])
+{
+    const float *p = tris + 9 * (size_t)i;
+#pragma unroll
+    for (int v = 0; v < 3; v++) t[v] = {p[3 * v], p[3 * v + 1], p[3 * v + 2]};
+}
+
+struct Pose {
+    float R[9], t[3];
+};
+
+__device__ __forceinline__ V3<float> xform_f32(const Pose &P, V3<float> x)
+{
+    return {__builtin_fmaf(P.R[0], x.x, __builtin_fmaf(P.R[1], x.y, __builtin_fmaf(P.R[2], x.z, P.t[0]))),
+            __builtin_fmaf(P.R[3], x.x, __builtin_fmaf(P.R[4], x.y, __builtin_fmaf(P.R[5], x.z, P.t[1]))),
+            __builtin_fmaf(P.R[6], x.x, __builtin_fmaf(P.R[7], x.y, __builtin_fmaf(P.R[8], x.z, P.t[2])))};
+}
+__device__ __forceinline__ V3<double> xform_f64(const Pose &P, V3<float> x)
+{
+    double X = x.x, Y = x.y, Z = x.z;
+    return {fma((double)P.R[0], X, fma((double)P.R[1], Y, fma((double)P.R[2], Z, (double)P.t[0]))),
+            fma((double)P.R[3], X, fma((double)P.R[4], Y, fma((double)P.R[5], Z, (double)P.t[1]))),
+            fma((double)P.R[6], X, fma((double)P.R[7], Y, fma((double)P.R[8], Z, (double)P.t[2])))};
+}
+__device__ __forceinline__ V3<double> to64(V3<float> x) { return {(double)x.x, (double)x.y, (double)x.z}; }
+
+// 16-bit reciprocal for n in [1, 8]: (x * r) >> 16 == x / n for x < 64
+__device__ __forceinline__ uint32_t recip16(uint32_t n) { return (65536u + n - 1u) / n; }
+
+struct Counters {
+    unsigned long long bv_tests = 0, tri_tests = 0, tri_fp64 = 0, expansions = 0, node_bytes = 0, tri_bytes = 0;
+    uint32_t max_entries = 0, max_records = 0;
+};
+
+// ---------------------------------------------------------------------------
+// the traversal kernel
+// ---------------------------------------------------------------------------
+template <int K, int BITS, int MODE, bool GLOBAL>
+__global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits lim, int pass)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint32_t lane = __lane_id();
+    const Layout LY = make_layout(K, MODE, lim);
+    unsigned char *base = GLOBAL ? (q.ws.garena + (size_t)blockIdx.x * q.ws.garena_stride) : lds_raw;
+    float *coef = (float *)(base + LY.coef);
+    uint32_t *upidx = (uint32_t *)(base + LY.upidx);
+    float *vtU = (float *)(base + LY.vtU);
+    float *vtL = (float *)(base + LY.vtL);
+    uint32_t *frame_end = (uint32_t *)(base + LY.frame_end);
+    uint32_t *rtopo = (uint32_t *)(base + LY.rtopo);
+    float *rbnd = (float *)(base + LY.rbnd);
+    float *ta = (float *)(base + LY.ta);
+    uint32_t *ent = (uint32_t *)(base + LY.ent);
+    float *ent_lb = (float *)(base + LY.ent_lb);
+    uint2 *lq = (uint2 *)(base + LY.lq);
+    float *lq_lb = (float *)(base + LY.lq_lb);
+    uint32_t *scratch = (uint32_t *)(base + LY.scratch);
+
+    const DevModel &MA = q.A;
+    const DevModel &MB = q.B;
+    WsHeader *hdr = q.ws.hdr;
+    Counters cnt;
+    const uint32_t lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
+    const uint32_t code_bytes_A = 4 + MA.stride, code_bytes_B = 4 + MB.stride;
+
+    for (;;) {
+        // ---- next pose ----
+        uint32_t pose;
+        if (pass == 0) {
+            uint32_t p = 0;
+            if (lane == 0) p = atomicAdd(&hdr->pose_next, 1u);
+            pose = uni(p);
+            if (pose >= q.n_poses) break;
+        } else {
+            uint32_t p = 0;
+            if (lane == 0) p = atomicAdd(&hdr->fallback_next, 1u);
+            p = uni(p);
+            if (p >= uni(*(volatile uint32_t *)&hdr->fallback_count) || p >= q.n_poses) break;
+            pose = uni(q.ws.fallback_list[p]);
+        }
+        Pose P;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+#pragma unroll
+            for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
+            P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
+        }
+        pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, coef, upidx, vtU, vtL, lane);
+        // distance: FP32 leaf-distance error bound e (generous multiple of
+        // the transform and closest-point rounding at this coordinate scale)
+        const float tnorm = sqrtf(P.t[0] * P.t[0] + P.t[1] * P.t[1] + P.t[2] * P.t[2]);
+        const float e_abs = 256.0f * 0x1p-24f * (tnorm + 3.5f * (MA.max_abs + MB.max_abs));
+        const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
+
+        // ---- root frame: record 0 = A's root, record 1 = B's root ----
+        if (lane < 2) {
+            const DevModel &M = lane == 0 ? MA : MB;
+            uint32_t tw = M.topo[0];
+            float bnd[2 * K];
+            decode_node<K, BITS>(M, 0, tw, (const float *)nullptr, bnd);
+            rtopo[lane] = tw;
+#pragma unroll
+            for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
+        }
+        if (lane == 0) frame_end[0] = 2;
+        wave_sync();
+
+        // current frame description (wave-uniform)
+        uint32_t f_id = 0, f_base = 0, f_nslots = 1, f_nA = 1, f_total_tasks = 1;
+        uint32_t s_aoff[EMAX] = {0, 0, 0, 0}, s_na[EMAX] = {1, 0, 0, 0};
+        uint32_t s_boff[EMAX] = {1, 0, 0, 0}, s_nb[EMAX] = {1, 0, 0, 0};
+        uint32_t s_tpre[EMAX + 1] = {0, 64, 64, 64, 64};
+        bool have_frame = true;
+        uint32_t top = 0, lq_count = 0;
+        bool hit = false, overflow = false, pair_overflow = false;
+        float best32 = INFINITY;
+        double best64 = INFINITY;
+
+        for (;;) {
+            if (have_frame) {
+                have_frame = false;
+                // -------- transform A's records of the frame into B's frame --------
+                for (uint32_t t = lane; t < f_nA * K; t += WAVE) {
+                    uint32_t i = t / K, k = t - i * K;
+                    const float *b = rbnd + (size_t)(f_base + i) * 2 * K;
+                    uint32_t up = upidx[k];
+                    float U = vtU[k], L = vtL[k];
+#pragma unroll
+                    for (int m = 0; m < 3; m++) {
+                        uint32_t ix = (up >> (8 * m)) & 0xFFu;
+                        float c = coef[3 * k + m];
+                        U = __builtin_fmaf(c, b[ix], U);
+                        L = __builtin_fmaf(c, b[ix ^ 1u], L);
+                    }
+                    ta[2 * K * i + 2 * k] = L;
+                    ta[2 * K * i + 2 * k + 1] = U;
+                }
+                wave_sync();
+                // -------- one child pair per lane --------
+                const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
+                bool survive = false;
+                float lb = 0.0f;
+                uint32_t recA = 0, recB = 0;
+                if (lane < f_total_tasks) {
+                    uint32_t s = (lane >= s_tpre[1]) + (lane >= s_tpre[2]) + (lane >= s_tpre[3]);
+                    uint32_t nb = s == 0 ? s_nb[0] : s == 1 ? s_nb[1] : s == 2 ? s_nb[2] : s_nb[3];
+                    uint32_t ao = s == 0 ? s_aoff[0] : s == 1 ? s_aoff[1] : s == 2 ? s_aoff[2] : s_aoff[3];
+                    uint32_t bo = s == 0 ? s_boff[0] : s == 1 ? s_boff[1] : s == 2 ? s_boff[2] : s_boff[3];
+                    uint32_t tp = s == 0 ? s_tpre[0] : s == 1 ? s_tpre[1] : s == 2 ? s_tpre[2] : s_tpre[3];
+                    uint32_t local = lane - tp;
+                    uint32_t i = (local * recip16(nb)) >> 16, j = local - i * nb;
+                    uint32_t ia = ao + i;
+                    recA = f_base + ia;
+                    recB = f_base + bo + j;
+                    const float *tA = ta + 2 * K * ia;
+                    const float *bB = rbnd + (size_t)recB * 2 * K;
+                    if (MODE == MODE_DIST) {
+                        float g = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < K; k++) {
+                            float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
+                            gk *= (k < 3 ? 1.0f : w_diag);
+                            g = fmaxf(g, gk);
+                        }
+                        lb = g * (1.0f - 0x1p-20f);
+                        survive = lb <= tau;
+                    } else {
+                        bool sep = false;
+#pragma unroll
+                        for (int k = 0; k < K; k++) sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
+                        survive = !sep;
+                    }
+                }
+                cnt.bv_tests += f_total_tasks;
+                // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
+                uint32_t tA_w = 0, tB_w = 0;
+                bool ll = false;
+                if (survive) {
+                    tA_w = rtopo[recA];
+                    tB_w = rtopo[recB];
+                    ll = topo_leaf(tA_w) && topo_leaf(tB_w);
+                }
+                uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
+                uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
+                if (lq_count + n_ll > lim.leafq || top + n_nd > lim.entries) {
+                    overflow = true;
+                    break;
+                }
+                if (survive && ll) {
+                    uint32_t slot = lq_count + mbcnt(m_ll);
+                    lq[slot] = make_uint2(tA_w, tB_w);
+                    if (MODE == MODE_DIST) lq_lb[slot] = lb;
+                }
+                if (survive && !ll) {
+                    uint32_t slot = top + mbcnt(m_nd);
+                    ent[slot] = recA | (recB << REC_BITS) | (f_id << (2 * REC_BITS));
+                    if (MODE == MODE_DIST) ent_lb[slot] = lb;
+                }
+                lq_count += n_ll;
+                if (MODE == MODE_DIST && n_nd > 1) {
+                    // put the closest new pair on top of the stack
+                    float mlb = wave_min((survive && !ll) ? lb : INFINITY);
+                    uint64_t win = __ballot(survive && !ll && lb == mlb);
+                    uint32_t wl = win ? (uint32_t)__ffsll((unsigned long long)win) - 1u : 0u;
+                    uint32_t wslot = top + (uint32_t)__popcll(m_nd & ((1ull << wl) - 1ull));
+                    uint32_t last = top + n_nd - 1;
+                    wave_sync();
+                    if (lane == 0 && win && wslot != last) {
+                        uint32_t e0 = ent[wslot];
+                        float l0 = ent_lb[wslot];
+                        ent[wslot] = ent[last];
+                        ent_lb[wslot] = ent_lb[last];
+                        ent[last] = e0;
+                        ent_lb[last] = l0;
+                    }
+                }
+                top += n_nd;
+                cnt.max_entries = max(cnt.max_entries, top);
+                wave_sync();
+            }
+            if (MODE == MODE_BOOL && hit) break;
+            if (MODE == MODE_DIST && best64 == 0.0) break;
+
+            // -------- leaf step --------
+            uint32_t trig = lq_trigger_full < 1 ? 1 : lq_trigger_full;
+            if (MODE == MODE_DIST && best32 == INFINITY) trig = 1;
+            if (lq_count > 0 && (lq_count >= trig || top == 0)) {
+                const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
+                uint32_t n_avail = min(lq_count, (uint32_t)WAVE);
+                uint32_t tasks = 0;
+                uint2 e = make_uint2(0, 0);
+                if (lane < n_avail) {
+                    uint32_t slot = lq_count - 1 - lane;
+                    e = lq[slot];
+                    tasks = topo_count(e.x) * topo_count(e.y);
+                    if (MODE == MODE_DIST && lq_lb[slot] > tau) tasks = 0;
+                }
+                uint32_t incl = wave_incl_scan(tasks, lane);
+                uint64_t m_take = __ballot(lane < n_avail && incl <= (uint32_t)WAVE);
+                uint32_t n_take = __popcll(m_take);
+                uint32_t total = n_take ? lane_of(incl, (int)n_take - 1) : 0u;
+                if (lane < n_take) scratch[lane] = incl;
+                wave_sync();
+                const uint32_t lq_old = lq_count;
+                lq_count -= n_take;
+                int res = 0;
+                bool active = lane < total;
+                uint32_t triA = 0, triB = 0;
+                V3<float> a[3], b[3];
+                if (active) {
+                    // entry of this lane: first e with incl[e] > lane
+                    uint32_t lo = 0, hi = n_take - 1;
+                    while (lo < hi) {
+                        uint32_t mid = (lo + hi) >> 1;
+                        if (scratch[mid] > lane) hi = mid; else lo = mid + 1;
+                    }
+                    uint32_t excl = lo ? scratch[lo - 1] : 0u;
+                    uint2 le = lq[lq_old - 1 - lo];
+                    uint32_t local = lane - excl, nb = topo_count(le.y);
+                    uint32_t ia = (local * recip16(nb)) >> 16, ib = local - ia * nb;
+                    triA = topo_first(le.x) + ia;
+                    triB = topo_first(le.y) + ib;
+                    V3<float> a0[3];
+                    load_tri(MA.tris, triA, a0);
+                    load_tri(MB.tris, triB, b);
+#pragma unroll
+                    for (int v = 0; v < 3; v++) a[v] = xform_f32(P, a0[v]);
+                    if (MODE != MODE_DIST) {
+                        res = tri_tri_f32(a, b);
+                        if (res == 2) {
+                            V3<double> a64[3], b64[3];
+#pragma unroll
+                            for (int v = 0; v < 3; v++) {
+                                a64[v] = xform_f64(P, a0[v]);
+                                b64[v] = to64(b[v]);
+                            }
+                            res = tri_tri_f64(a64, b64) ? 3 : 4;  // 3/4: FP64-decided hit/miss
+                        }
+                    } else {
+                        int s32 = tri_tri_f32(a, b);
+                        float d32 = 0.0f;
+                        if (s32 == 0) {
+                            V3<float> ar[3], br[3];
+#pragma unroll
+                            for (int v = 0; v < 3; v++) {
+                                ar[v] = vsub(a[v], a[0]);
+                                br[v] = vsub(b[v], a[0]);
+                            }
+                            d32 = sqrtf(tri_tri_dist2(ar, br));
+                        }
+                        res = __float_as_int(d32);
+                    }
+                }
+                cnt.tri_tests += total;
+                cnt.tri_bytes += 72ull * total;
+                if (MODE == MODE_BOOL || MODE == MODE_PAIRS) {
+                    bool h = active && (res == 1 || res == 3);
+                    cnt.tri_fp64 += __popcll(__ballot(active && res >= 3));
+                    uint64_t mh = __ballot(h);
+                    if (mh) hit = true;
+                    if (MODE == MODE_PAIRS && mh) {
+                        uint32_t nh = __popcll(mh);
+                        uint32_t b0 = 0;
+                        if (lane == 0) b0 = atomicAdd(&hdr->pair_count, nh);
+                        b0 = uni(b0);
+                        if (h) {
+                            uint32_t idx = b0 + mbcnt(mh);
+                            if (idx < q.pair_cap)
+                                q.ws.pair_raw[idx] = make_uint4(pose | ((uint32_t)pass << 31), MA.perm[triA], MB.perm[triB], 0u);
+                        }
+                        if (b0 + nh > q.pair_cap) pair_overflow = true;
+                    }
+                } else {
+                    float d32 = active ? __int_as_float(res) : INFINITY;
+                    best32 = fminf(best32, wave_min(d32));
+                    const float tau2 = add_up(best32, 2.0f * e_abs);
+                    bool refine = active && d32 <= tau2;
+                    cnt.tri_fp64 += __popcll(__ballot(refine));
+                    double d64 = INFINITY;
+                    if (refine) {
+                        V3<float> a0[3];
+                        load_tri(MA.tris, triA, a0);
+                        V3<double> a64[3], b64[3];
+#pragma unroll
+                        for (int v = 0; v < 3; v++) {
+                            a64[v] = xform_f64(P, a0[v]);
+                            b64[v] = to64(b[v]);
+                        }
+                        if (tri_tri_f64(a64, b64)) {
+                            d64 = 0.0;
+                        } else {
+                            V3<double> ar[3], br[3];
+#pragma unroll
+                            for (int v = 0; v < 3; v++) {
+                                ar[v] = vsub(a64[v], a64[0]);
+                                br[v] = vsub(b64[v], a64[0]);
+                            }
+                            d64 = sqrt(tri_tri_dist2(ar, br));
+                        }
+                    }
+                    best64 = fmin(best64, wave_min(d64));
+                }
+                wave_sync();
+                continue;
+            }
+            if (top == 0) break;
+
+            // -------- node step: pop a batch of entries, decode their children --------
+            const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
+            uint32_t my_e = 0, my_na = 0, my_nb = 0, my_tasks = 0, my_pA = 0, my_pB = 0;
+            if (lane < (uint32_t)EMAX && lane < top) {
+                my_e = ent[top - 1 - lane];
+                uint32_t rA = my_e & REC_MASK, rB = (my_e >> REC_BITS) & REC_MASK;
+                my_pA = rtopo[rA];
+                my_pB = rtopo[rB];
+                my_na = topo_leaf(my_pA) ? 1u : topo_count(my_pA);
+                my_nb = topo_leaf(my_pB) ? 1u : topo_count(my_pB);
+                my_tasks = my_na * my_nb;
+                if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_tasks = my_na = my_nb = 0;
+            }
+            // greedy prefix of at most EMAX entries whose tests fit in one wave
+            uint32_t n_pop = 0, acc = 0;
+            uint32_t e_s[EMAX], na_s[EMAX], nb_s[EMAX], pA_s[EMAX], pB_s[EMAX];
+#pragma unroll
+            for (int s = 0; s < EMAX; s++) {
+                e_s[s] = lane_of(my_e, s);
+                na_s[s] = lane_of(my_na, s);
+                nb_s[s] = lane_of(my_nb, s);
+                pA_s[s] = lane_of(my_pA, s);
+                pB_s[s] = lane_of(my_pB, s);
+                uint32_t tk = lane_of(my_tasks, s);
+                bool ok = (uint32_t)s < top && n_pop == (uint32_t)s && acc + tk <= (uint32_t)WAVE;
+                if (ok) {
+                    n_pop++;
+                    acc += tk;
+                }
+            }
+            // new frame sits on top of the frame of the next remaining entry
+            uint32_t remaining = top - n_pop;
+            uint32_t new_id = 0, new_base = 0;
+            if (remaining > 0) {
+                uint32_t f_below = uni(ent[remaining - 1]) >> (2 * REC_BITS);
+                new_id = f_below + 1;
+                new_base = uni(frame_end[f_below]);
+            }
+            // slots of the new frame: A lists first, then B lists
+            uint32_t nA_tot = 0, nB_tot = 0, ns = 0, tasks_tot = 0;
+            uint32_t n_aoff[EMAX] = {0, 0, 0, 0}, n_na[EMAX] = {0, 0, 0, 0}, n_nb[EMAX] = {0, 0, 0, 0};
+            uint32_t n_src[EMAX] = {0, 0, 0, 0}, n_tpre[EMAX + 1] = {64, 64, 64, 64, 64};
+#pragma unroll
+            for (int s = 0; s < EMAX; s++) {
+                if ((uint32_t)s < n_pop && na_s[s] > 0) {
+#pragma unroll
+                    for (int d = 0; d < EMAX; d++)
+                        if ((uint32_t)d == ns) {
+                            n_aoff[d] = nA_tot;
+                            n_na[d] = na_s[s];
+                            n_nb[d] = nb_s[s];
+                            n_src[d] = (uint32_t)s;
+                            n_tpre[d] = tasks_tot;
+                        }
+                    nA_tot += na_s[s];
+                    nB_tot += nb_s[s];
+                    tasks_tot += na_s[s] * nb_s[s];
+                    ns++;
+                }
+            }
+            uint32_t n_boff[EMAX] = {0, 0, 0, 0};
+            {
+                uint32_t accb = nA_tot;
+#pragma unroll
+                for (int d = 0; d < EMAX; d++) {
+                    n_boff[d] = accb;
+                    accb += n_nb[d];
+                }
+            }
+            top = remaining;
+            if (ns == 0) continue;  // every popped entry was culled
+            uint32_t total_rec = nA_tot + nB_tot;
+            if (new_id >= (uint32_t)MAX_FRAMES || new_base + total_rec > lim.records ||
+                new_base + total_rec > REC_MASK + 1u) {
+                overflow = true;
+                break;
+            }
+            // decode: one lane per new record (register staging: the new
+            // frame may overwrite the popped entries' own frames)
+            uint32_t my_topo = 0;
+            float my_b[2 * K];
+            bool dec = lane < total_rec;
+            if (dec) {
+                bool sideA = lane < nA_tot;
+                uint32_t r = sideA ? lane : lane - nA_tot;
+                uint32_t d = 0;
+#pragma unroll
+                for (int x = 1; x < EMAX; x++) {
+                    uint32_t off = sideA ? n_aoff[x] : n_boff[x] - nA_tot;
+                    if ((uint32_t)x < ns && r >= off) d = (uint32_t)x;
+                }
+                uint32_t off = sideA ? (d == 0 ? n_aoff[0] : d == 1 ? n_aoff[1] : d == 2 ? n_aoff[2] : n_aoff[3])
+                                     : (d == 0 ? n_boff[0] : d == 1 ? n_boff[1] : d == 2 ? n_boff[2] : n_boff[3]) - nA_tot;
+                uint32_t c = r - off;
+                uint32_t src = d == 0 ? n_src[0] : d == 1 ? n_src[1] : d == 2 ? n_src[2] : n_src[3];
+                uint32_t e = src == 0 ? e_s[0] : src == 1 ? e_s[1] : src == 2 ? e_s[2] : e_s[3];
+                uint32_t prec = sideA ? (e & REC_MASK) : ((e >> REC_BITS) & REC_MASK);
+                uint32_t ptopo = rtopo[prec];
+                const float *pb = rbnd + (size_t)prec * 2 * K;
+                if (topo_leaf(ptopo)) {
+                    my_topo = ptopo;
+#pragma unroll
+                    for (int k = 0; k < 2 * K; k++) my_b[k] = pb[k];
+                } else {
+                    const DevModel &M = sideA ? MA : MB;
+                    uint32_t node = topo_first(ptopo) + c;
+                    my_topo = M.topo[node];
+                    decode_node<K, BITS>(M, node, my_topo, pb, my_b);
+                }
+            }
+            wave_sync();
+            if (dec) {
+                rtopo[new_base + lane] = my_topo;
+#pragma unroll
+                for (int k = 0; k < 2 * K; k++) rbnd[(size_t)(new_base + lane) * 2 * K + k] = my_b[k];
+            }
+            if (lane == 0) frame_end[new_id] = new_base + total_rec;
+            // counters: children fetched by the expanded sides
+            {
+                unsigned long long nbytes = 0;
+#pragma unroll
+                for (int d = 0; d < EMAX; d++) {
+                    if ((uint32_t)d < ns) {
+                        uint32_t src = n_src[d];
+                        uint32_t pa = src == 0 ? pA_s[0] : src == 1 ? pA_s[1] : src == 2 ? pA_s[2] : pA_s[3];
+                        uint32_t pb2 = src == 0 ? pB_s[0] : src == 1 ? pB_s[1] : src == 2 ? pB_s[2] : pB_s[3];
+                        if (!topo_leaf(pa)) nbytes += (unsigned long long)topo_count(pa) * code_bytes_A;
+                        if (!topo_leaf(pb2)) nbytes += (unsigned long long)topo_count(pb2) * code_bytes_B;
+                    }
+                }
+                cnt.node_bytes += nbytes;
+                cnt.expansions += ns;
+            }
+            cnt.max_records = max(cnt.max_records, new_base + total_rec);
+            wave_sync();
+            // the new frame becomes the current one
+            f_id = new_id;
+            f_base = new_base;
+            f_nslots = ns;
+            f_nA = nA_tot;
+            f_total_tasks = tasks_tot;
+#pragma unroll
+            for (int d = 0; d < EMAX; d++) {
+                s_aoff[d] = n_aoff[d];
+                s_na[d] = n_na[d];
+                s_boff[d] = n_boff[d];
+                s_nb[d] = n_nb[d];
+                s_tpre[d] = n_tpre[d];
+            }
+            s_tpre[EMAX] = 64;
+            // slots past the last one never match a lane
+#pragma unroll
+            for (int d = 1; d < EMAX; d++)
+                if ((uint32_t)d >= ns) s_tpre[d] = 64;
+            (void)f_nslots;
+            have_frame = true;
+        }
+
+        // ---- outputs for this pose ----
+        if (lane == 0) {
+            uint8_t st = 0;
+            if (overflow) {
+                if (pass == 0 && !q.no_fallback) {
+                    uint32_t slot = atomicAdd(&hdr->fallback_count, 1u);
+                    q.ws.fallback_list[slot] = pose;
+                    q.ws.fell_back[pose] = 1;
+                    st = 0xFF;  // resolved by the fallback pass
+                } else {
+                    st = 1;  // CBVH_POSE_STACK_OVERFLOW
+                }
+            } else if (pair_overflow) {
+                st = 2;  // CBVH_POSE_PAIR_OVERFLOW
+            }
+            if (st != 0xFF) {
+                q.status[pose] = st;
+                if (MODE != MODE_DIST) q.hit[pose] = hit ? 1 : 0;
+                else q.dist[pose] = (float)best64;
+            }
+        }
+        wave_sync();
+    }
+    // ---- flush counters ----
+    if (lane == 0) {
+        atomicAdd(&hdr->counters[C_BV_TESTS], cnt.bv_tests);
+        atomicAdd(&hdr->counters[C_TRI_TESTS], cnt.tri_tests);
+        atomicAdd(&hdr->counters[C_TRI_FP64], cnt.tri_fp64);
+        atomicAdd(&hdr->counters[C_EXPANSIONS], cnt.expansions);
+        atomicAdd(&hdr->counters[C_NODE_BYTES], cnt.node_bytes);
+        atomicAdd(&hdr->counters[C_TRI_BYTES], cnt.tri_bytes);
+        atomicMax(&hdr->counters[C_MAX_ENTRIES], (unsigned long long)cnt.max_entries);
+        atomicMax(&hdr->counters[C_MAX_RECORDS], (unsigned long long)cnt.max_records);
+        if (pass == 1) {
+            uint32_t fb = *(volatile uint32_t *)&hdr->fallback_count;
+            if (blockIdx.x == 0) atomicAdd(&hdr->counters[C_FALLBACK_POSES], (unsigned long long)fb);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace init and pair-list finalize
+// ---------------------------------------------------------------------------
+__global__ void init_kernel(WsHeader *hdr, uint8_t *fell_back, uint32_t *pair_cnt, uint32_t *pair_cursor, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < sizeof(WsHeader) / 4) ((uint32_t *)hdr)[i] = 0u;
+    if (i < n) {
+        fell_back[i] = 0;
+        if (pair_cnt) {
+            pair_cnt[i] = 0;
+            pair_cursor[i] = 0;
+        }
+    }
+}
+
+__device__ __forceinline__ bool pair_valid(const uint4 &r, const uint8_t *fell_back)
+{
+    uint32_t pose = r.x & 0x7FFFFFFFu, pass = r.x >> 31;
+    return pass == 1 || !fell_back[pose];
+}
+
+__global__ void pair_count_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, const uint8_t *fell_back,
+                                  uint32_t *cnt)
+{
+    uint32_t total = min(hdr->pair_count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        uint4 r = raw[i];
+        if (pair_valid(r, fell_back)) atomicAdd(&cnt[r.x & 0x7FFFFFFFu], 1u);
+    }
+}
+
+// exclusive scan of n counts by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void pair_scan_kernel(const uint32_t *cnt, uint32_t *offsets, uint32_t n)
+{
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b = 0; b < n; b += 1024) {
+        uint32_t i = b + threadIdx.x;
+        uint32_t v = i < n ? cnt[i] : 0u;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < 1024; o <<= 1) {
+            uint32_t t = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n) offsets[i] = carry + part[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offsets[n] = carry;
+}
+
+__global__ void pair_scatter_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, const uint8_t *fell_back,
+                                    const uint32_t *offsets, uint32_t *cursor, unsigned long long *keys)
+{
+    uint32_t total = min(hdr->pair_count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        uint4 r = raw[i];
+        if (!pair_valid(r, fell_back)) continue;
+        uint32_t pose = r.x & 0x7FFFFFFFu;
+        uint32_t pos = offsets[pose] + atomicAdd(&cursor[pose], 1u);
+        keys[pos] = ((unsigned long long)r.y << 32) | r.z;
+    }
+}
+
+// sort each pose's keys (triA << 32 | triB) and write (pose, triA, triB);
+// bitonic sort in LDS for segments up to 4096 keys, else in global memory
+constexpr uint32_t SORT_LDS = 4096;
+__global__ __launch_bounds__(256) void pair_sort_kernel(const uint32_t *offsets, unsigned long long *keys,
+                                                        uint32_t *out, uint32_t n)
+{
+    __shared__ unsigned long long sk[SORT_LDS];
+    for (uint32_t pose = blockIdx.x; pose < n; pose += gridDim.x) {
+        uint32_t b = offsets[pose], e = offsets[pose + 1], len = e - b;
+        if (len == 0) continue;
+        uint32_t p2 = 1;
+        while (p2 < len) p2 <<= 1;
+        unsigned long long *arr = keys + b;
+        bool in_lds = p2 <= SORT_LDS;
+        if (in_lds) {
+            for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) sk[i] = i < len ? arr[i] : ~0ull;
+            __syncthreads();
+            for (uint32_t k = 2; k <= p2; k <<= 1)
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+                        uint32_t l = i ^ j;
+                        if (l > i) {
+                            bool up = (i & k) == 0;
+                            unsigned long long x = sk[i], y = sk[l];
+                            if ((x > y) == up) {
+                                sk[i] = y;
+                                sk[l] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) arr[i] = sk[i];
+            __syncthreads();
+        } else {
+            // odd-even transposition in global memory (large segments are rare)
+            for (uint32_t round = 0; round < len; round++) {
+                for (uint32_t i = 2 * threadIdx.x + (round & 1); i + 1 < len; i += 2 * blockDim.x) {
+                    unsigned long long x = arr[i], y = arr[i + 1];
+                    if (x > y) {
+                        arr[i] = y;
+                        arr[i + 1] = x;
+                    }
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+            unsigned long long k = arr[i];
+            out[3 * (size_t)(b + i)] = pose;
+            out[3 * (size_t)(b + i) + 1] = (uint32_t)(k >> 32);
+            out[3 * (size_t)(b + i) + 2] = (uint32_t)k;
+        }
+        __syncthreads();
+    }
+}
+
+// decode every node: one thread per treelet walks its nodes in order (the
+// top group is absolute, every other node's parent lies earlier in the
+// same treelet), the random access that treelets give
+template <int K, int BITS>
+__global__ void decode_all_kernel(DevModel M, float *out)
+{
+    uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (BITS == 0) {
+        for (uint32_t i = t; i < M.n_nodes; i += gridDim.x * blockDim.x) {
+            float b[2 * K];
+            decode_node<K, 0>(M, i, M.topo[i], (const float *)nullptr, b);
+            for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
+        }
+        return;
+    }
+    if (t >= M.n_treelets) return;
+    uint32_t first = M.treelets[t], end = M.treelets[t + 1];
+    for (uint32_t i = first; i < end; i++) {
+        uint32_t w = M.topo[i];
+        if (topo_abs(w)) {
+            float b[2 * K];
+            decode_node<K, BITS>(M, i, w, (const float *)nullptr, b);
+            for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
+        }
+        if (!topo_leaf(w)) {
+            uint32_t c0 = topo_first(w), nc = topo_count(w);
+            if (c0 >= end) continue;  // children start another treelet (absolute there)
+            for (uint32_t c = 0; c < nc; c++) {
+                uint32_t node = c0 + c;
+                float b[2 * K];
+                decode_node<K, BITS>(M, node, M.topo[node], out + (size_t)i * 2 * K, b);
+                for (int k = 0; k < 2 * K; k++) out[(size_t)node * 2 * K + k] = b[k];
+            }
+        }
+    }
+}
+
+template <int K, int BITS, int MODE>
+hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+{
+    if (pass == 0) {
+        Layout L = make_layout(K, MODE, lim);
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus < 1) cus = 256;
+        uint32_t per_cu = (uint32_t)(160u * 1024u / (L.total + 256u));
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > 32) per_cu = 32;
+        uint32_t grid = (uint32_t)cus * per_cu;
+        if (grid > q.n_poses) grid = q.n_poses;
+        if (grid < 1) grid = 1;
+        hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE, false>), dim3(grid), dim3(WAVE), L.total, s, q, lim, 0);
+    } else {
+        StackLimits gl = fallback_limits(K);
+        hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE, true>), dim3(q.ws.garena_waves), dim3(WAVE), 0, s, q, gl, 1);
+    }
+    return hipGetLastError();
+}
+
+template <int K, int BITS>
+hipError_t launch_mode(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+{
+    switch (q.mode) {
+    case MODE_BOOL: return launch_traverse<K, BITS, MODE_BOOL>(q, lim, s, pass);
+    case MODE_PAIRS: return launch_traverse<K, BITS, MODE_PAIRS>(q, lim, s, pass);
+    default: return launch_traverse<K, BITS, MODE_DIST>(q, lim, s, pass);
+    }
+}
+
+hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+{
+    uint32_t K = q.A.K, bits = q.A.bits;
+    if (K == 3) {
+        if (bits == 0) return launch_mode<3, 0>(q, lim, s, pass);
+        if (bits == 8) return launch_mode<3, 8>(q, lim, s, pass);
+        return launch_mode<3, 16>(q, lim, s, pass);
+    }
+    if (bits == 0) return launch_mode<9, 0>(q, lim, s, pass);
+    if (bits == 8) return launch_mode<9, 8>(q, lim, s, pass);
+    return launch_mode<9, 16>(q, lim, s, pass);
+}
+
+}  // namespace
+
+size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return make_layout(K, mode, lim).total; }
+
+StackLimits default_limits(uint32_t K)
+{
+    if (K == 9) return StackLimits{128, 512, 128};
+    return StackLimits{256, 768, 128};
+}
+
+StackLimits fallback_limits(uint32_t K)
+{
+    (void)K;
+    return StackLimits{8191, 16384, 128};
+}
+
+uint32_t fallback_waves() { return 32; }
+
+hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t s, uint32_t *pair_out,
+                        uint32_t *pair_offsets)
+{
+    const uint32_t n = q.n_poses;
+    {
+        uint32_t threads = 256, items = n > 96 ? n : 96;
+        hipLaunchKernelGGL(init_kernel, dim3((items + threads - 1) / threads), dim3(threads), 0, s, q.ws.hdr,
+                           q.ws.fell_back, q.mode == MODE_PAIRS ? q.ws.pair_cnt : nullptr,
+                           q.mode == MODE_PAIRS ? q.ws.pair_cursor : nullptr, n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_any(q, lim, s, 0);
+    if (e != hipSuccess) return e;
+    if (!q.no_fallback) {
+        e = launch_any(q, lim, s, 1);
+        if (e != hipSuccess) return e;
+    }
+    if (q.mode == MODE_PAIRS) {
+        hipLaunchKernelGGL(pair_count_kernel, dim3(256), dim3(256), 0, s, q.ws.hdr, q.ws.pair_raw, q.pair_cap,
+                           q.ws.fell_back, q.ws.pair_cnt);
+        hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, s, q.ws.pair_cnt, pair_offsets, n);
+        hipLaunchKernelGGL(pair_scatter_kernel, dim3(256), dim3(256), 0, s, q.ws.hdr, q.ws.pair_raw, q.pair_cap,
+                           q.ws.fell_back, pair_offsets, q.ws.pair_cursor, q.ws.pair_keys);
+        uint32_t g = n < 2048 ? n : 2048;
+        if (g < 1) g = 1;
+        hipLaunchKernelGGL(pair_sort_kernel, dim3(g), dim3(256), 0, s, pair_offsets, q.ws.pair_keys, pair_out, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_decode_all(const DevModel &m, float *out, hipStream_t s)
+{
+    uint32_t threads = 64;
+    uint32_t items = m.bits == 0 ? m.n_nodes : m.n_treelets;
+    dim3 grid((items + threads - 1) / threads);
+    if (m.K == 3) {
+        if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<3, 0>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<3, 8>), grid, dim3(threads), 0, s, m, out);
+        else hipLaunchKernelGGL((decode_all_kernel<3, 16>), grid, dim3(threads), 0, s, m, out);
+    } else {
+        if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<9, 0>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<9, 8>), grid, dim3(threads), 0, s, m, out);
+        else hipLaunchKernelGGL((decode_all_kernel<9, 16>), grid, dim3(threads), 0, s, m, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cbvh

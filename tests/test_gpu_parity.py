@@ -1,0 +1,261 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the FP64 oracle.
+
+- decode: every node's decoded bounds bit-identical to the oracle's decoder;
+- tiny workload (1,280 vs 1,280 triangles, AABB BF4 leaf 1, 8-bit and FP32):
+  booleans and sorted colliding-pair lists equal the oracle's on all 256
+  margin-filtered poses;
+- scaled workload (100k-triangle tori, 18-DOP BF8 leaf 4, 16-bit and FP32):
+  all 16,384 poses in one launch; booleans equal the oracle's on a sample of
+  poses accepted by the pose-level margin; compressed == uncompressed on all;
+- proximity workload (50k icosphere vs 50k torus, AABB BF4 leaf 1, 8-bit and
+  FP32): distances within 1e-5 relative of the oracle on a sample of
+  separated poses; compressed and uncompressed bit-identical on all;
+- failure paths forced from the host (tiny stack, tiny pair buffer), empty
+  and degenerate inputs, determinism.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from synth import configs, meshes, poses
+
+torch = pytest.importorskip("torch")
+cb = pytest.importorskip("paper_2012_05348_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _models(cfg, compressed=True, **over):
+    w = configs.WORKLOADS[cfg]
+    (va, ta), (vb, tb) = W.meshes(cfg)
+    kw = dict(bv=W.BV[w.bv], branching=w.branching, leaf_size=w.leaf_size, bits=w.bits if compressed else 0)
+    kw.update(over)
+    return cb.Model.build(va, ta, **kw).to(DEV), cb.Model.build(vb, tb, **kw).to(DEV)
+
+
+_model_cache = {}
+
+
+def models(cfg, compressed=True):
+    key = (cfg, compressed)
+    if key not in _model_cache:
+        _model_cache[key] = _models(cfg, compressed)
+    return _model_cache[key]
+
+
+# ---------------------------------------------------------------- decode
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("compressed", [True, False])
+def test_decode_all_bit_exact(cfg, compressed):
+    _log(f"decode cfg={cfg} compressed={compressed}")
+    for m in models(cfg, compressed):
+        got = m.decode_all().cpu().numpy()
+        ref = oracle.blob_decode(m.blob())
+        assert got.shape == ref.shape
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+# ---------------------------------------------------------------- tiny workload
+def _pairs_per_pose(pairs, offs, n):
+    return [pairs[offs[i]:offs[i + 1]] for i in range(n)]
+
+
+@pytest.mark.parametrize("compressed", [True, False])
+def test_tiny_pairs_match_oracle(compressed):
+    P, _ = W.config0_poses()
+    A, B = W.oracle_meshes(0)
+    ma, mb = models(0, compressed)
+    _log(f"tiny pairs compressed={compressed}")
+    hit, st, pairs, offs = cb.collide(ma, mb, torch.from_numpy(P).to(DEV), flags=cb.PAIRS, pair_capacity=1 << 18)
+    torch.cuda.synchronize()
+    hit, st, pairs, offs = (x.cpu().numpy() for x in (hit, st, pairs, offs))
+    assert (st == 0).all()
+    assert offs[0] == 0 and (np.diff(offs) >= 0).all()
+    n_hit = 0
+    for i, p in enumerate(P):
+        ref = oracle.collide_pairs(A, B, p)
+        seg = pairs[offs[i]:offs[i + 1]]
+        assert (seg[:, 0] == i).all()
+        assert np.array_equal(seg[:, 1:].astype(np.uint32), ref), f"pose {i}"
+        assert bool(hit[i]) == (len(ref) > 0)
+        n_hit += bool(hit[i])
+    assert n_hit == 128
+
+
+@pytest.mark.parametrize("compressed", [True, False])
+def test_tiny_booleans_match_oracle(compressed):
+    P, _ = W.config0_poses()
+    A, B = W.oracle_meshes(0)
+    ma, mb = models(0, compressed)
+    hit, st = cb.collide(ma, mb, torch.from_numpy(P).to(DEV), flags=cb.EARLY_EXIT)
+    ref, _ = oracle.collide_batch(A, B, P)
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(hit.cpu().numpy().astype(bool), ref)
+
+
+# ---------------------------------------------------------------- scaled workload
+@pytest.fixture(scope="module")
+def scaled_results():
+    w = configs.WORKLOADS[1]
+    P = w.raw_poses()
+    Pd = torch.from_numpy(P).to(DEV)
+    out = {}
+    for compressed in (True, False):
+        ma, mb = models(1, compressed)
+        _log(f"scaled collide compressed={compressed}")
+        ws = cb.workspace(ma, mb, len(P))
+        hit, st = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT, ws=ws)
+        stats = cb.cbvh_stats(ws.buf)
+        out[compressed] = (hit.cpu().numpy(), st.cpu().numpy(), stats)
+    return P, out
+
+
+def test_scaled_booleans_match_oracle_on_sample(scaled_results):
+    P, out = scaled_results
+    w = configs.WORKLOADS[1]
+    (va, ta), (vb, tb) = W.meshes(1)
+    A, B = W.oracle_meshes(1)
+    idx = W.sample_indices(len(P), 256, seed=1)
+    cls = oracle.classify_batch(A, B, P[idx], w.margin(va, vb))
+    keep = idx[cls != oracle.MARGINAL]
+    assert len(keep) > 200
+    ref, _ = oracle.collide_batch(A, B, P[keep])
+    for compressed in (True, False):
+        hit, st, _ = out[compressed]
+        assert (st == 0).all()
+        assert np.array_equal(hit[keep].astype(bool), ref)
+    assert 0 < ref.sum() < len(ref)
+
+
+def test_scaled_compressed_equals_uncompressed(scaled_results):
+    _, out = scaled_results
+    assert np.array_equal(out[True][0], out[False][0])
+    sc, su = out[True][2], out[False][2]
+    assert sc["bv_tests"] > 0 and su["bv_tests"] > 0
+    _log(f"scaled stats compressed={sc} uncompressed={su}")
+
+
+# ---------------------------------------------------------------- proximity workload
+@pytest.fixture(scope="module")
+def proximity_results():
+    w = configs.WORKLOADS[2]
+    P = w.raw_poses()
+    Pd = torch.from_numpy(P).to(DEV)
+    out = {}
+    for compressed in (True, False):
+        ma, mb = models(2, compressed)
+        _log(f"proximity distance compressed={compressed}")
+        ws = cb.workspace(ma, mb, len(P))
+        d, st = cb.distance(ma, mb, Pd, ws=ws)
+        out[compressed] = (d.cpu().numpy(), st.cpu().numpy(), cb.cbvh_stats(ws.buf))
+    return P, out
+
+
+def test_proximity_distances_match_oracle_on_sample(proximity_results):
+    P, out = proximity_results
+    w = configs.WORKLOADS[2]
+    (va, ta), (vb, tb) = W.meshes(2)
+    A, B = W.oracle_meshes(2)
+    idx = W.sample_indices(len(P), 128, seed=2)
+    cls = oracle.classify_batch(A, B, P[idx], w.margin(va, vb))
+    ref, _ = oracle.distance_batch(A, B, P[idx])
+    sep = cls == oracle.SEPARATED
+    col = cls == oracle.COLLIDING
+    assert sep.sum() > 80
+    for compressed in (True, False):
+        d, st, _ = out[compressed]
+        assert (st == 0).all()
+        got = d[idx].astype(np.float64)
+        rel = np.abs(got[sep] - ref[sep]) / ref[sep]
+        assert rel.max() <= 1e-5, (rel.max(), idx[sep][np.argmax(rel)])
+        assert (got[col] == 0).all()
+
+
+def test_proximity_compressed_equals_uncompressed(proximity_results):
+    _, out = proximity_results
+    assert np.array_equal(out[True][0].view(np.uint32), out[False][0].view(np.uint32))
+    _log(f"proximity stats compressed={out[True][2]} uncompressed={out[False][2]}")
+
+
+# ---------------------------------------------------------------- edge cases and failure paths
+def test_empty_batch_is_a_noop():
+    ma, mb = models(0)
+    P = torch.zeros((0, 3, 4), dtype=torch.float32, device=DEV)
+    hit, st = cb.collide(ma, mb, P)
+    assert hit.numel() == 0
+
+
+def test_single_triangle_meshes():
+    a = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], dtype=np.float32)
+    t = np.array([[0, 1, 2]], dtype=np.uint32)
+    ma = cb.Model.build(a, t, bits=8).to(DEV)
+    mb = cb.Model.build(a, t, bits=8).to(DEV)
+    # B's triangle pierced by A's triangle turned upright / A lifted clear of B
+    up = np.array([[1, 0, 0, 0.2], [0, 0, -1, 0.2], [0, 1, 0, -0.5]], dtype=np.float32)
+    lift = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0.25]], dtype=np.float32)
+    P = np.stack([up, lift])
+    hit, st = cb.collide(ma, mb, torch.from_numpy(P).to(DEV))
+    d, dst = cb.distance(ma, mb, torch.from_numpy(P).to(DEV))
+    assert hit.cpu().tolist() == [1, 0]
+    dd = d.cpu().numpy()
+    assert dd[0] == 0.0 and abs(dd[1] - 0.25) <= 1e-6
+    A, B = oracle.Mesh(a, t), oracle.Mesh(a, t)
+    assert oracle.collide(A, B, up)[0] and not oracle.collide(A, B, lift)[0]
+
+
+def test_forced_stack_overflow_falls_back_to_the_global_stack():
+    P, _ = W.config0_poses()
+    A, B = W.oracle_meshes(0)
+    ma, mb = models(0)
+    Pd = torch.from_numpy(P).to(DEV)
+    try:
+        cb.cbvh_set_stack_limits(entries=6, records=12)
+        ws = cb.workspace(ma, mb, len(P), cb.PAIRS, 1 << 18)
+        hit, st, pairs, offs = cb.collide(ma, mb, Pd, flags=cb.PAIRS, pair_capacity=1 << 18, ws=ws)
+        stats = cb.cbvh_stats(ws.buf)
+        hit2, st2 = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT | cb.NO_FALLBACK)
+    finally:
+        cb.cbvh_set_stack_limits(0, 0)
+    assert stats["fallback_poses"] > 0
+    st, pairs, offs = st.cpu().numpy(), pairs.cpu().numpy(), offs.cpu().numpy()
+    assert (st == 0).all()
+    for i, p in enumerate(P):
+        assert np.array_equal(pairs[offs[i]:offs[i + 1], 1:].astype(np.uint32), oracle.collide_pairs(A, B, p))
+    st2 = st2.cpu().numpy()
+    assert (st2 == cb.POSE_STACK_OVERFLOW).any()
+    ref, _ = oracle.collide_batch(A, B, P)
+    ok = st2 == 0
+    assert np.array_equal(hit2.cpu().numpy()[ok].astype(bool), ref[ok])
+
+
+def test_pair_buffer_overflow_is_flagged_per_pose():
+    P, _ = W.config0_poses()
+    A, B = W.oracle_meshes(0)
+    ma, mb = models(0)
+    cap = 500
+    hit, st, pairs, offs = cb.collide(ma, mb, torch.from_numpy(P).to(DEV), flags=cb.PAIRS, pair_capacity=cap)
+    st, pairs, offs = st.cpu().numpy(), pairs.cpu().numpy(), offs.cpu().numpy()
+    assert (st == cb.POSE_PAIR_OVERFLOW).any()
+    assert offs[-1] <= cap
+    for i, p in enumerate(P):
+        if st[i] == 0:
+            assert np.array_equal(pairs[offs[i]:offs[i + 1], 1:].astype(np.uint32), oracle.collide_pairs(A, B, p))
+
+
+def test_results_do_not_depend_on_batch_composition():
+    w = configs.WORKLOADS[1]
+    P = w.raw_poses(2048)
+    ma, mb = models(1)
+    full, _ = cb.collide(ma, mb, torch.from_numpy(P).to(DEV))
+    part, _ = cb.collide(ma, mb, torch.from_numpy(P[::7].copy()).to(DEV))
+    again, _ = cb.collide(ma, mb, torch.from_numpy(P).to(DEV))
+    assert np.array_equal(full.cpu().numpy()[::7], part.cpu().numpy())
+    assert np.array_equal(full.cpu().numpy(), again.cpu().numpy())
