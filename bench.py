@@ -1,0 +1,263 @@
+"""Benchmark: collision queries on the scaled workload (two 100k-triangle noisy
+tori, 18-DOP BVHs, branching 8, leaf size 4, 16-bit predictor-corrector codes,
+16,384 seeded rigid poses, boolean answers with early exit) on one GPU.
+
+One step = one cbvh_collide call over the whole pose batch (per-pose setup,
+traversal, leaf tests, outputs).  Inputs are resident in HBM before timing.
+Prints one JSON line.  The uncompressed (FP32 descriptor) twin, the tiny
+pair-list workload and the proximity (distance) workload are timed after the
+main measurement and reported as extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "poses/sec + BV-pair tests/sec (compressed vs uncompressed BVH); p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2012_05348_amd/csrc/traverse.hip", "paper_2012_05348_amd/csrc/geom.h",
+                  "paper_2012_05348_amd/csrc/format.h", "paper_2012_05348_amd/csrc/kernels.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_dop18_16bit_torus100k.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _models(cb, w, bits, dev):
+    (va, ta), (vb, tb) = w.meshes()
+    bv = cb.AABB if w.bv == "aabb" else cb.DOP18
+    ma = cb.Model.build(va, ta, bv=bv, branching=w.branching, leaf_size=w.leaf_size, bits=bits).to(dev)
+    mb = cb.Model.build(vb, tb, bv=bv, branching=w.branching, leaf_size=w.leaf_size, bits=bits).to(dev)
+    return ma, mb
+
+
+T0 = time.perf_counter()
+
+
+def progress(msg):
+    print(f"[bench {time.perf_counter() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps, warmup):
+    """W untimed steps, then K steps between synchronizations; per-step events
+    on the launching (current) stream give the per-call device time."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = [a.elapsed_time(b) for a, b in evs]
+    return wall, dev_ms
+
+
+def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0):
+    import torch
+    ma, mb = _models(cb, w, bits, dev)
+    P = torch.from_numpy(w.raw_poses()).to(dev)
+    n = P.shape[0]
+    ws = cb.workspace(ma, mb, n, flags, pair_capacity, dev)
+    hit = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    pairs = offs = None
+    if flags & cb.PAIRS:
+        pairs = torch.empty((pair_capacity, 3), dtype=torch.int32, device=dev)
+        offs = torch.empty(n + 1, dtype=torch.int32, device=dev)
+
+    def step():
+        cb.cbvh_collide(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, hit, pairs, pair_capacity, offs, st, ws.buf)
+
+    progress(f"collide {w.name.split(':')[0]} bits={bits} n={n}: warmup")
+    wall, dev_ms = time_steps(step, steps, warmup)
+    stats = cb.cbvh_stats(ws.buf)
+    status_ok = bool((st == 0).all().item())
+    progress(f"  {steps} steps, {np.mean(dev_ms):.3f} ms/call, stats {stats}")
+    info = ma.info()
+    return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=status_ok, hits=int(hit.sum().item()),
+                info=info, descriptor_bytes=info["descriptor_bytes"] + mb.info()["descriptor_bytes"])
+
+
+def run_distance(cb, w, bits, dev, steps, warmup):
+    import torch
+    ma, mb = _models(cb, w, bits, dev)
+    P = torch.from_numpy(w.raw_poses()).to(dev)
+    n = P.shape[0]
+    ws = cb.workspace(ma, mb, n, 0, 0, dev)
+    d = torch.empty(n, dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def step():
+        cb.cbvh_distance(ma.handle, ma.dev, mb.handle, mb.dev, P, n, 0, d, st, ws.buf)
+
+    progress(f"distance {w.name.split(':')[0]} bits={bits} n={n}: warmup")
+    wall, dev_ms = time_steps(step, steps, warmup)
+    stats = cb.cbvh_stats(ws.buf)
+    progress(f"  {steps} steps, {np.mean(dev_ms):.3f} ms/call, stats {stats}")
+    return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=bool((st == 0).all().item()),
+                descriptor_bytes=ma.info()["descriptor_bytes"] + mb.info()["descriptor_bytes"])
+
+
+def summarize(r, steps):
+    ms = float(np.mean(r["dev_ms"]))
+    s = r["stats"]
+    per_launch_bytes = s["node_bytes"] + s["tri_bytes"]
+    return {
+        "poses_per_sec": r["n"] * steps / r["wall"],
+        "bv_tests_per_sec": s["bv_tests"] / (ms * 1e-3),
+        "ms_per_call_median": float(np.median(r["dev_ms"])),
+        "ms_per_call_min": float(np.min(r["dev_ms"])),
+        "bv_tests_per_call": s["bv_tests"],
+        "tri_tests_per_call": s["tri_tests"],
+        "tri_fp64_per_call": s["tri_fp64"],
+        "expansions_per_call": s["expansions"],
+        "algorithmic_bytes_per_call": per_launch_bytes,
+        "bw_equivalent_GBs": per_launch_bytes / (ms * 1e-3) / 1e9,
+        "descriptor_bytes": r["descriptor_bytes"],
+        "fallback_poses": s["fallback_poses"],
+        "status_ok": r["ok"],
+    }
+
+
+def cpu_baseline(w, threads, budget_s=10.0):
+    """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
+    host: repeated passes over the workload's poses until about budget_s
+    seconds of work have run (at most 8 passes; one pass for slow workloads)."""
+    import oracle
+    progress("cpu baseline (oracle)")
+    (va, ta), (vb, tb) = w.meshes()
+    A, B = oracle.Mesh(va, ta), oracle.Mesh(vb, tb)
+    P = w.raw_poses()
+    n = len(P)
+    # size the sample from a short probe so slow workloads stay bounded
+    probe = P[: min(n, 256)]
+    t0 = time.perf_counter()
+    run = oracle.distance_batch if w.query == "distance" else oracle.collide_batch
+    run(A, B, probe, threads=threads)
+    per_pose = (time.perf_counter() - t0) / len(probe)
+    n_sample = int(min(n, max(256, budget_s / max(per_pose, 1e-9))))
+    passes = 1 if n_sample < n else int(max(1, min(64, budget_s / max(per_pose * n, 1e-9))))
+    sample = P[:n_sample]
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        run(A, B, sample, threads=threads)
+    dt = time.perf_counter() - t0
+    progress(f"  oracle: {passes} pass(es) over {n_sample} poses in {dt:.2f} s")
+    return {"value": passes * n_sample / dt, "unit": "poses/s", "cores": threads, "kind": "oracle",
+            "sample": f"{passes} pass(es) over the first {n_sample} of the {n} poses ({dt:.1f} s); "
+                      "FP64 Algorithm 1 on the oracle's own binary AABB tree, early exit per pose"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="skip the uncompressed twin and the other workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (HBM counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the query batch is sharded by poses across GPUs with no exchange "
+              "beyond gathering outputs, and this build runs on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2012_05348_amd as cb
+    from synth import configs
+
+    dev = torch.device("cuda:0")
+    w = configs.WORKLOADS[1]
+    main_r = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT)
+    main_s = summarize(main_r, args.steps)
+    ms_per_step = main_r["wall"] / args.steps * 1e3
+    kavg_ms = float(np.mean(main_r["dev_ms"]))
+    algo_bytes = main_s["algorithmic_bytes_per_call"]
+    achieved = algo_bytes / (kavg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": main_s["poses_per_sec"],
+        "unit": "poses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "scaled collision: noisy torus 100k tri vs noisy torus 100k tri, 18-DOP BF8 leaf 4, "
+                        "16-bit predictor-corrector codes, 16384 poses, booleans with early exit",
+            "poses": main_r["n"], "bv": "dop18", "branching": 8, "leaf_size": 4, "bits": 16,
+            "parallelism": "one wavefront per pose",
+        },
+        "bv_tests_per_sec": main_s["bv_tests_per_sec"],
+        "compressed": main_s,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": "traverse_kernel<9,16,bool>", "kernel_avg_ms": kavg_ms,
+            "algorithmic_bytes_per_launch": algo_bytes,
+        },
+    }
+    if not args.no_extra:
+        unc = run_collide(cb, w, 0, dev, args.steps, args.warmup, cb.EARLY_EXIT)
+        out["uncompressed"] = summarize(unc, args.steps)
+        out["uncompressed"]["hits_equal"] = unc["hits"] == main_r["hits"]
+        out["compression"] = {
+            "descriptor_bytes_compressed": main_s["descriptor_bytes"],
+            "descriptor_bytes_fp32": out["uncompressed"]["descriptor_bytes"],
+            "ratio": out["uncompressed"]["descriptor_bytes"] / main_s["descriptor_bytes"],
+            "bv_test_inflation": main_s["bv_tests_per_call"] / max(1, out["uncompressed"]["bv_tests_per_call"]),
+            "speedup_vs_fp32": main_s["poses_per_sec"] / out["uncompressed"]["poses_per_sec"],
+        }
+        w0, w2 = configs.WORKLOADS[0], configs.WORKLOADS[2]
+        tiny = run_collide(cb, w0, w0.bits, dev, 10, 2, cb.PAIRS, pair_capacity=1 << 20)
+        out["tiny_pairs"] = summarize(tiny, 10)
+        for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32")):
+            pr = run_distance(cb, w2, bits, dev, 5, 1)
+            out[key] = summarize(pr, 5)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, threads=min(16, os.cpu_count() or 1))
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

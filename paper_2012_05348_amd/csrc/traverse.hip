@@ -76,7 +76,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 // per-wave state layout (identical on host and device)
 // ---------------------------------------------------------------------------
 struct Layout {
-    uint32_t coef, upidx, vtU, vtL, misc, frame_end, rtopo, rbnd, ta, ent, ent_lb, lq, lq_lb, scratch, total;
+    uint32_t coef, upidx, vtU, vtL, misc, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
 };
 
 __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
@@ -97,6 +97,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
     L.ta = take(8 * K * TA_MAX);
+    L.tsph = take(16 * TA_MAX);
     L.ent = take(4 * lim.entries);
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
@@ -296,6 +297,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
     uint32_t *rtopo = (uint32_t *)(base + LY.rtopo);
     float *rbnd = (float *)(base + LY.rbnd);
     float *ta = (float *)(base + LY.ta);
+    float4 *tsph = (float4 *)(base + LY.tsph);
     uint32_t *ent = (uint32_t *)(base + LY.ent);
     float *ent_lb = (float *)(base + LY.ent_lb);
     uint2 *lq = (uint2 *)(base + LY.lq);
@@ -337,6 +339,9 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         const float tnorm = sqrtf(P.t[0] * P.t[0] + P.t[1] * P.t[1] + P.t[2] * P.t[2]);
         const float e_abs = 256.0f * 0x1p-24f * (tnorm + 3.5f * (MA.max_abs + MB.max_abs));
         const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
+        // absolute rounding allowance of the sphere bound below
+        const float e_sph = 64.0f * 0x1p-24f *
+                            (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
 
         // ---- root frame: record 0 = A's root, record 1 = B's root ----
         if (lane < 2) {
@@ -381,6 +386,15 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     ta[2 * K * i + 2 * k] = L;
                     ta[2 * K * i + 2 * k + 1] = U;
                 }
+                if (MODE == MODE_DIST && lane < f_nA) {
+                    // circumscribed sphere of the record's box, centre moved by the pose
+                    const float *b = rbnd + (size_t)(f_base + lane) * 2 * K;
+                    V3<float> c = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
+                    float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
+                    float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                    V3<float> cw = xform_f32(P, c);
+                    tsph[lane] = make_float4(cw.x, cw.y, cw.z, r);
+                }
                 wave_sync();
                 // -------- one child pair per lane --------
                 const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
@@ -408,7 +422,14 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                             gk *= (k < 3 ? 1.0f : w_diag);
                             g = fmaxf(g, gk);
                         }
-                        lb = g * (1.0f - 0x1p-20f);
+                        // second lower bound: distance of the circumscribed spheres
+                        float4 sa = tsph[ia];
+                        float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
+                        float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
+                        float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                        float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
+                        float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
+                        lb = fmaxf(g * (1.0f - 0x1p-20f), gs);
                         survive = lb <= tau;
                     } else {
                         bool sep = false;
@@ -615,7 +636,10 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 pA_s[s] = lane_of(my_pA, s);
                 pB_s[s] = lane_of(my_pB, s);
                 uint32_t tk = lane_of(my_tasks, s);
-                bool ok = (uint32_t)s < top && n_pop == (uint32_t)s && acc + tk <= (uint32_t)WAVE;
+                // proximity queries dive one expansion at a time until a first
+                // leaf distance exists: without a bound nothing is culled
+                bool dive = MODE == MODE_DIST && best32 == INFINITY && s > 0;
+                bool ok = !dive && (uint32_t)s < top && n_pop == (uint32_t)s && acc + tk <= (uint32_t)WAVE;
                 if (ok) {
                     n_pop++;
                     acc += tk;
@@ -1014,10 +1038,10 @@ StackLimits default_limits(uint32_t K)
 StackLimits fallback_limits(uint32_t K)
 {
     (void)K;
-    return StackLimits{8191, 16384, 128};
+    return StackLimits{4096, 8192, 128};
 }
 
-uint32_t fallback_waves() { return 32; }
+uint32_t fallback_waves() { return 128; }
 
 hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t s, uint32_t *pair_out,
                         uint32_t *pair_offsets)
