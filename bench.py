@@ -98,7 +98,7 @@ def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0):
                 info=info, descriptor_bytes=info["descriptor_bytes"] + mb.info()["descriptor_bytes"])
 
 
-def run_distance(cb, w, bits, dev, steps, warmup):
+def run_distance(cb, w, bits, dev, steps, warmup, flags=0):
     import torch
     ma, mb = _models(cb, w, bits, dev)
     P = torch.from_numpy(w.raw_poses()).to(dev)
@@ -108,7 +108,7 @@ def run_distance(cb, w, bits, dev, steps, warmup):
     st = torch.empty(n, dtype=torch.uint8, device=dev)
 
     def step():
-        cb.cbvh_distance(ma.handle, ma.dev, mb.handle, mb.dev, P, n, 0, d, st, ws.buf)
+        cb.cbvh_distance(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, d, st, ws.buf)
 
     progress(f"distance {w.name.split(':')[0]} bits={bits} n={n}: warmup")
     wall, dev_ms = time_steps(step, steps, warmup)
@@ -134,7 +134,8 @@ def summarize(r, steps):
         "algorithmic_bytes_per_call": per_launch_bytes,
         "bw_equivalent_GBs": per_launch_bytes / (ms * 1e-3) / 1e9,
         "descriptor_bytes": r["descriptor_bytes"],
-        "fallback_poses": s["fallback_poses"],
+        "donated_items": s["donated_items"],
+        "max_unit_steps": s["max_pose_steps"],
         "status_ok": r["ok"],
     }
 

@@ -113,11 +113,11 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 /* Query flags */
 #define CBVH_EARLY_EXIT 0x1u /* collide: stop a pose at its first colliding triangle pair */
 #define CBVH_PAIRS 0x2u      /* collide: report every colliding triangle pair */
-#define CBVH_NO_FALLBACK 0x4u /* do not re-run stack-overflowing poses with the large global stack */
+#define CBVH_NO_SPLIT 0x4u   /* keep every pose in one wavefront: never hand pending work to other wavefronts */
 
 /* Per-pose status bytes written by the queries */
 #define CBVH_POSE_OK 0u
-#define CBVH_POSE_STACK_OVERFLOW 1u /* traversal stack exhausted even in the fallback; results invalid */
+#define CBVH_POSE_STACK_OVERFLOW 1u /* traversal state exhausted and no room to donate it; results invalid */
 #define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
 
 /* Workspace bytes (device, caller-owned, 256-byte aligned) for a query on
@@ -125,7 +125,16 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 size_t cbvh_workspace_bytes(const cbvh_model *a, const cbvh_model *b, uint32_t n_poses, uint32_t flags,
                             uint32_t pair_capacity);
 
-/* Collision detection for a batch of poses (Algorithm 1; leaf test is the
+/* How a query runs: one launch of persistent wavefronts.  Each takes poses
+ * from a queue and traverses one pose at a time.  Once no pose is left, a
+ * wavefront waits for work items: busy wavefronts hand the pending node
+ * pairs nearest their roots (with their decoded bounds) to waiting ones, and
+ * a pose whose traversal state would overflow LDS hands over all of its
+ * pending pairs.  Per-pose answers are merged in device memory, so results
+ * do not depend on how the work was split.  The workspace holds the queue:
+ * calls that share a workspace must not overlap in time.
+ *
+ * Collision detection for a batch of poses (Algorithm 1; leaf test is the
  * closed triangle-triangle intersection, touching counts).
  *   a, a_dev: moving model and its uploaded copy; b, b_dev: fixed model.
  *   poses:    device float32 [n][3][4].
@@ -163,18 +172,23 @@ typedef struct {
     uint64_t expansions;     /* node-pair expansions (children fetched and decoded) */
     uint64_t node_bytes;     /* descriptor + topology bytes the expansions fetched */
     uint64_t tri_bytes;      /* triangle bytes the leaf tests fetched */
-    uint64_t fallback_poses; /* poses re-run on the large global-memory stack */
+    uint64_t donated_items;  /* pending node/leaf pairs handed from a busy wavefront to waiting ones */
     uint64_t max_entries;    /* deepest traversal stack seen (entries) */
     uint64_t max_records;    /* most decoded-BV records live at once */
-    uint64_t reserved[7];
+    uint64_t t_start;        /* device wall clock (100 MHz ticks) when the first wave took a pose */
+    uint64_t t_drain;        /* ... when a wave first found the pose queue empty */
+    uint64_t t_end;          /* ... when the last wave exited */
+    uint64_t max_pose_steps; /* most traversal steps (node + leaf) one work unit needed */
+    uint64_t wait_timeouts;  /* 1 if a wavefront gave up waiting for work (never expected; results invalid) */
+    uint64_t reserved[2];
 } cbvh_stats_t;
 
 cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream);
 
-/* Test hook: cap the fast (LDS) traversal stack at `entries` entries and
- * `records` decoded-BV records (0 restores the defaults), so tests can force
- * the overflow path from the host.  Affects subsequent queries of this
- * process. */
+/* Test hook: cap the per-wavefront (LDS) traversal state at `entries`
+ * pending node pairs (0 or >= 72) and `records` decoded BVs (0 or >= 20);
+ * 0 restores the defaults.  Lets tests force the donation path from the
+ * host.  Affects subsequent queries of this process. */
 cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records);
 
 /* Thread-local message describing the last failure (never NULL). */

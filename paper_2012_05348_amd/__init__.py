@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbvh.so")
 
 AABB, DOP18 = 0, 1
-EARLY_EXIT, PAIRS, NO_FALLBACK = 0x1, 0x2, 0x4
+EARLY_EXIT, PAIRS, NO_SPLIT = 0x1, 0x2, 0x4
 POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_CAPACITY", 5: "E_UNSUPPORTED", 6: "E_FORMAT"}
 
@@ -46,8 +46,9 @@ class ModelInfo(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("bv_tests", "tri_tests", "tri_fp64", "expansions", "node_bytes",
-                                           "tri_bytes", "fallback_poses", "max_entries", "max_records")] + \
-               [("reserved", C.c_uint64 * 7)]
+                                           "tri_bytes", "donated_items", "max_entries", "max_records",
+                                           "t_start", "t_drain", "t_end", "max_pose_steps", "wait_timeouts")] + \
+               [("reserved", C.c_uint64 * 2)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}

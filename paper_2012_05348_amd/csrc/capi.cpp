@@ -56,19 +56,19 @@ cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
     return d;
 }
 
-cbvh::StackLimits current_limits(uint32_t K)
+cbvh::StackLimits current_limits(uint32_t K, int mode)
 {
-    cbvh::StackLimits l = cbvh::default_limits(K);
+    cbvh::StackLimits l = cbvh::default_limits(K, mode);
     uint32_t e = g_limit_entries.load(), r = g_limit_records.load();
     if (e) l.entries = e;
     if (r) l.records = r;
     return l;
 }
 
-// workspace carving: [header | fallback_list | fell_back | pair buffers | fallback stacks]
+// workspace carving: [header | item queue | per-pose answers | pair buffers]
 struct WsPlan {
-    uint64_t hdr, fallback_list, fell_back, pair_raw, pair_cnt, pair_cursor, pair_keys, garena, total;
-    uint64_t garena_stride;
+    uint64_t hdr, items, ready, hitw, best32, best64, pair_raw, pair_cnt, pair_cursor, pair_keys, total;
+    uint32_t item_cap, item_words;
 };
 
 WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
@@ -80,16 +80,23 @@ WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
         o = align_up(o + bytes, 256);
         return r;
     };
+    p.item_words = cbvh::item_words(K);
+    // donated work items (slots are not reused within a query): four per
+    // pose plus slack; a donation that finds the queue full is not made
+    uint64_t cap = 4ull * n + 262144ull;
+    if (cap > (1ull << 24)) cap = 1ull << 24;
+    p.item_cap = (uint32_t)cap;
+    bool dist = mode == cbvh::MODE_DIST, pairs = mode == cbvh::MODE_PAIRS;
     p.hdr = take(sizeof(cbvh::WsHeader));
-    p.fallback_list = take(4ull * n);
-    p.fell_back = take(n);
-    bool pairs = mode == cbvh::MODE_PAIRS;
+    p.items = take((uint64_t)p.item_cap * p.item_words * 4ull);
+    p.ready = take(4ull * p.item_cap);
+    p.hitw = take(mode == cbvh::MODE_BOOL ? 4ull * n : 0);
+    p.best32 = take(dist ? 4ull * n : 0);
+    p.best64 = take(dist ? 8ull * n : 0);
     p.pair_raw = take(pairs ? 16ull * pair_cap : 0);
     p.pair_cnt = take(pairs ? 4ull * n : 0);
     p.pair_cursor = take(pairs ? 4ull * n : 0);
     p.pair_keys = take(pairs ? 8ull * pair_cap : 0);
-    p.garena_stride = align_up(cbvh::wave_state_bytes(K, mode, cbvh::fallback_limits(K)), 256);
-    p.garena = take(p.garena_stride * cbvh::fallback_waves());
     p.total = o;
     return p;
 }
@@ -137,18 +144,20 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.dist = dist;
     q.status = status;
     q.pair_cap = pair_cap;
-    q.no_fallback = (flags & CBVH_NO_FALLBACK) ? 1u : 0u;
+    q.no_split = (flags & CBVH_NO_SPLIT) ? 1u : 0u;
     q.ws.hdr = (cbvh::WsHeader *)(w + plan.hdr);
-    q.ws.fallback_list = (uint32_t *)(w + plan.fallback_list);
-    q.ws.fell_back = w + plan.fell_back;
+    q.ws.items = (uint32_t *)(w + plan.items);
+    q.ws.ready = (uint32_t *)(w + plan.ready);
+    q.ws.item_cap = plan.item_cap;
+    q.ws.item_words = plan.item_words;
+    q.ws.hitw = (uint32_t *)(w + plan.hitw);
+    q.ws.best32 = (unsigned int *)(w + plan.best32);
+    q.ws.best64 = (unsigned long long *)(w + plan.best64);
     q.ws.pair_raw = (uint4 *)(w + plan.pair_raw);
     q.ws.pair_cnt = (uint32_t *)(w + plan.pair_cnt);
     q.ws.pair_cursor = (uint32_t *)(w + plan.pair_cursor);
     q.ws.pair_keys = (unsigned long long *)(w + plan.pair_keys);
-    q.ws.garena = w + plan.garena;
-    q.ws.garena_stride = plan.garena_stride;
-    q.ws.garena_waves = cbvh::fallback_waves();
-    cbvh::StackLimits lim = current_limits(a->hdr.K);
+    cbvh::StackLimits lim = current_limits(a->hdr.K, mode);
     hipError_t e = cbvh::launch_query(q, lim, (hipStream_t)stream, pairs, pair_offsets);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return CBVH_OK;
@@ -279,7 +288,7 @@ cbvh_status cbvh_collide(const cbvh_model *a, const void *a_dev, const cbvh_mode
 {
     if ((flags & CBVH_PAIRS) && (flags & CBVH_EARLY_EXIT))
         return fail(CBVH_E_INVALID, "CBVH_PAIRS and CBVH_EARLY_EXIT are exclusive");
-    if (flags & ~(CBVH_EARLY_EXIT | CBVH_PAIRS | CBVH_NO_FALLBACK)) return fail(CBVH_E_INVALID, "unknown flag");
+    if (flags & ~(CBVH_EARLY_EXIT | CBVH_PAIRS | CBVH_NO_SPLIT)) return fail(CBVH_E_INVALID, "unknown flag");
     int mode = (flags & CBVH_PAIRS) ? cbvh::MODE_PAIRS : cbvh::MODE_BOOL;
     return run_query(a, a_dev, b, b_dev, poses, n, mode, flags, hit, nullptr, pairs, pair_capacity, pair_offsets,
                      pose_status, workspace, workspace_bytes, stream);
@@ -289,7 +298,7 @@ cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_mod
                           const float *poses, uint32_t n, uint32_t flags, float *dist, uint8_t *pose_status,
                           void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (flags & ~CBVH_NO_FALLBACK) return fail(CBVH_E_INVALID, "unknown flag");
+    if (flags & ~CBVH_NO_SPLIT) return fail(CBVH_E_INVALID, "unknown flag");
     return run_query(a, a_dev, b, b_dev, poses, n, cbvh::MODE_DIST, flags, nullptr, dist, nullptr, 0, nullptr,
                      pose_status, workspace, workspace_bytes, stream);
 }
@@ -320,16 +329,22 @@ cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats
     out->expansions = h.counters[cbvh::C_EXPANSIONS];
     out->node_bytes = h.counters[cbvh::C_NODE_BYTES];
     out->tri_bytes = h.counters[cbvh::C_TRI_BYTES];
-    out->fallback_poses = h.counters[cbvh::C_FALLBACK_POSES];
+    out->donated_items = h.counters[cbvh::C_DONATED];
     out->max_entries = h.counters[cbvh::C_MAX_ENTRIES];
     out->max_records = h.counters[cbvh::C_MAX_RECORDS];
+    out->t_start = h.counters[cbvh::C_T_START];
+    out->t_drain = h.counters[cbvh::C_T_DRAIN];
+    out->t_end = h.counters[cbvh::C_T_END];
+    out->max_pose_steps = h.counters[cbvh::C_MAX_POSE_STEPS];
+    out->wait_timeouts = h.error;
     return CBVH_OK;
 }
 
 cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records)
 {
     if (entries > 16384 || records > 8192) return fail(CBVH_E_INVALID, "limit too large");
-    if ((entries && entries < 2) || (records && records < 2)) return fail(CBVH_E_INVALID, "limit too small");
+    // one expansion of a single pair must always fit: up to 64 new entries and 16 records
+    if ((entries && entries < 72) || (records && records < 20)) return fail(CBVH_E_INVALID, "limit too small");
     g_limit_entries.store(entries);
     g_limit_records.store(records);
     return CBVH_OK;

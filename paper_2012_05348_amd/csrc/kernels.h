@@ -31,24 +31,33 @@ enum Counter : int {
     C_EXPANSIONS,
     C_NODE_BYTES,
     C_TRI_BYTES,
-    C_FALLBACK_POSES,
+    C_DONATED,         // work items handed from a busy wave to idle ones
     C_MAX_ENTRIES,
     C_MAX_RECORDS,
+    C_T_START,         // min wall clock (100 MHz) of a wave's first pose
+    C_T_DRAIN,         // min wall clock at which a wave found the pose queue empty
+    C_T_END,           // max wall clock of a wave's exit
+    C_MAX_POSE_STEPS,  // most node + leaf steps one work unit used
     C_NUM = 16
 };
 
-// Start of every workspace.
+// Start of every workspace.  The queue words that many waves hammer at
+// once sit on cache lines of their own.
 struct WsHeader {
     unsigned long long counters[C_NUM];
-    uint32_t pose_next;       // persistent-wave pose queue (main pass)
-    uint32_t fallback_count;  // poses queued for the global-stack pass
-    uint32_t fallback_next;   // fallback-pass queue
-    uint32_t pair_count;      // pairs appended (may exceed capacity)
-    uint32_t pad[60];
+    uint32_t pose_next;   // persistent-wave pose queue
+    uint32_t pair_count;  // pairs appended (may exceed capacity)
+    uint32_t error;       // a wave gave up waiting for an item (never expected)
+    uint32_t pad0[29];
+    uint32_t q_head;      // next item slot to claim (8-byte aligned: read together with q_tail)
+    uint32_t q_tail;      // next item slot to reserve
+    uint32_t pad1[30];
+    uint32_t pending;     // poses + published items not yet finished
+    uint32_t pad2[31];
 };
-static_assert(sizeof(WsHeader) == 384, "workspace header size");
+static_assert(sizeof(WsHeader) == 512, "workspace header size");
 
-// Limits of one wave's traversal state.
+// Limits of one wave's traversal state (LDS).
 struct StackLimits {
     uint32_t records;  // decoded-BV records (frames)
     uint32_t entries;  // pending node pairs
@@ -57,15 +66,17 @@ struct StackLimits {
 
 struct Workspace {
     WsHeader *hdr;
-    uint32_t *fallback_list;  // [n]
-    uint8_t *fell_back;       // [n]
-    uint4 *pair_raw;          // [pair_capacity] (pose | pass << 31, triA, triB, 0)
+    uint32_t *items;          // donated work items, item_words dwords each
+    uint32_t *ready;          // [item_cap] non-zero once an item is published
+    uint32_t item_cap;        // item slots (slot indices are never reused within a query)
+    uint32_t item_words;      // dwords per item
+    uint32_t *hitw;           // [n] collision found (read and written with atomics)
+    unsigned int *best32;     // [n] distance: FP32 bits of the best leaf distance so far
+    unsigned long long *best64;  // [n] distance: FP64 bits of the best refined distance
+    uint4 *pair_raw;          // [pair_capacity] (pose, triA, triB, 0)
     uint32_t *pair_cnt;       // [n]
     uint32_t *pair_cursor;    // [n]
     unsigned long long *pair_keys;  // [pair_capacity]
-    uint8_t *garena;          // fallback stacks
-    size_t garena_stride;     // bytes per fallback wave
-    uint32_t garena_waves;
 };
 
 struct QueryArgs {
@@ -77,18 +88,17 @@ struct QueryArgs {
     float *dist;
     uint8_t *status;
     uint32_t pair_cap;
-    uint32_t no_fallback;
+    uint32_t no_split;  // never donate work; exhausting the LDS stack then fails the pose
     Workspace ws;
 };
 
 // Bytes of one wave's traversal state for K slabs, a mode and limits.
 size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim);
-StackLimits default_limits(uint32_t K);
-StackLimits fallback_limits(uint32_t K);
-uint32_t fallback_waves();
+StackLimits default_limits(uint32_t K, int mode);
+uint32_t item_words(uint32_t K);
 
-// Enqueue the whole query on `stream` (init, main pass, fallback pass, and
-// for pair lists the count / scan / scatter / sort finalize).
+// Enqueue the whole query on `stream`: init, the traversal, and the finalize
+// (distances, or count / scan / scatter / sort of pair lists).
 hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t stream, uint32_t *pair_out,
                         uint32_t *pair_offsets);
 

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "format.h"
 #include "geom.h"
@@ -42,7 +43,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float unif(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 __device__ __forceinline__ uint32_t lane_of(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
 // a float not below the exact sum a + b
 __device__ __forceinline__ float add_up(float a, float b) { return nextafterf(a + b, INFINITY); }
@@ -97,7 +97,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
     L.ta = take(8 * K * TA_MAX);
-    L.tsph = take(16 * TA_MAX);
+    L.tsph = mode == MODE_DIST ? take(16 * TA_MAX) : o;
     L.ent = take(4 * lim.entries);
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
@@ -275,20 +275,70 @@ __device__ __forceinline__ V3<double> to64(V3<float> x) { return {(double)x.x, (
 __device__ __forceinline__ uint32_t recip16(uint32_t n) { return (65536u + n - 1u) / n; }
 
 struct Counters {
-    unsigned long long bv_tests = 0, tri_tests = 0, tri_fp64 = 0, expansions = 0, node_bytes = 0, tri_bytes = 0;
-    uint32_t max_entries = 0, max_records = 0;
+    unsigned long long bv_tests = 0, tri_tests = 0, tri_fp64 = 0, expansions = 0, node_bytes = 0, tri_bytes = 0,
+                       donated = 0;
+    uint32_t max_entries = 0, max_records = 0, max_steps = 0;
 };
 
+// A donated work item: a node pair that passed its BV test, with both
+// nodes' decoded bounds so that it is self-contained, or a leaf pair.
+//   u32 pose, u32 topo A, u32 topo B, f32 lower bound, f32 A[2K], f32 B[2K]
+__host__ __device__ constexpr uint32_t words_of_item(uint32_t K) { return 4u + 4u * K; }
+
+// Queue accesses between waves on different XCDs go through read-modify-write
+// atomics at device scope: they are performed at the device's coherence
+// point, where every XCD sees them in one order, whatever its own L2 holds.
+__device__ __forceinline__ uint32_t rmw_add(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t rmw_read(uint32_t *p) { return rmw_add(p, 0u); }
+__device__ __forceinline__ uint32_t rmw_xchg(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long rmw_read64(unsigned long long *p)
+{
+    return __hip_atomic_fetch_add(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this lane's memory operations have completed.  `dep` carries
+// the results of the atomics to wait for, so they are issued in their
+// returning form (complete once performed at the coherence point); the
+// memory clobber keeps the compiler from moving memory operations across.
+__device__ __forceinline__ void wait_mem(uint32_t dep) { asm volatile("s_waitcnt vmcnt(0)" : : "v"(dep) : "memory"); }
+
+// a waiting wave gives up (and flags the query) after this many 100 MHz
+// ticks without an item or the end of the query: 10 s, far beyond any query
+constexpr unsigned long long kWaitLimit = 1000000000ull;
+// node steps between two looks at the queue (for waiting waves to feed)
+constexpr uint32_t kDonatePeriod = 8;
+// steps between refreshes of the shared per-pose answer (hit flag or best distance)
+constexpr uint32_t kSyncPeriod = 4;
+// most items one balancing donation hands out
+constexpr uint32_t kMaxDonate = 32;
+// pose word of a queue slot that holds no work
+constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
+
 // ---------------------------------------------------------------------------
-// the traversal kernel
+// The traversal kernel: persistent waves.  Each wave takes poses from a queue
+// and traverses one pose at a time (a work unit).  Once the pose queue is
+// empty a wave takes the next slot of the item queue and waits for it to be
+// filled; busy waves look at the queue every few node steps and, while
+// slots wait, hand the bottom entries of their stack (the pairs nearest the
+// roots, i.e. the largest pending subtrees) to the waiting slots as items.
+// A unit whose next node step does not fit its LDS state hands over all of
+// its pending pairs and ends.  `pending` counts the poses and published items
+// not finished yet: it reaches zero exactly when no work is left, which
+// is when waiting waves exit.  Per-pose answers (hit flag, best distances)
+// are merged in device memory, so results do not depend on the split.
 // ---------------------------------------------------------------------------
-template <int K, int BITS, int MODE, bool GLOBAL>
-__global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits lim, int pass)
+template <int K, int BITS, int MODE>
+__global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits lim)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t lane = __lane_id();
     const Layout LY = make_layout(K, MODE, lim);
-    unsigned char *base = GLOBAL ? (q.ws.garena + (size_t)blockIdx.x * q.ws.garena_stride) : lds_raw;
+    unsigned char *base = lds_raw;
     float *coef = (float *)(base + LY.coef);
     uint32_t *upidx = (uint32_t *)(base + LY.upidx);
     float *vtU = (float *)(base + LY.vtU);
@@ -304,70 +354,217 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
     float *lq_lb = (float *)(base + LY.lq_lb);
     uint32_t *scratch = (uint32_t *)(base + LY.scratch);
 
+    constexpr uint32_t IW = words_of_item(K);       // dwords per item
+    constexpr uint32_t IPI = (uint32_t)WAVE / IW;   // items written per wave instruction
     const DevModel &MA = q.A;
     const DevModel &MB = q.B;
     WsHeader *hdr = q.ws.hdr;
     Counters cnt;
     const uint32_t lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
     const uint32_t code_bytes_A = 4 + MA.stride, code_bytes_B = 4 + MB.stride;
+    const bool can_donate = !q.no_split;
+    unsigned long long t_first = 0, t_drain = ~0ull;
+
+    // Publish items: reserve n slots of the item queue, fill them from
+    // entries [0, n_ent) and leaf pairs [0, n - n_ent), then mark them
+    // ready.  Returns the number of items published (n, or 0 if the queue
+    // is full; the slots reserved below its end are then published void).
+    auto publish = [&](uint32_t pose, uint32_t n, uint32_t n_ent, float best) -> uint32_t {
+        uint32_t first = 0, ok = 0, sink = 0;
+        if (lane == 0) {
+            first = rmw_add(&hdr->q_tail, n);
+            ok = first + n <= q.ws.item_cap && first + n >= first;
+            if (ok) {
+                sink ^= rmw_add(&hdr->pending, n);
+                if (MODE == MODE_DIST && best < INFINITY)
+                    sink ^= __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        ok = uni(ok);
+        first = uni(first);
+        if (!ok) {
+            for (uint32_t i = lane; i < n && first + i < q.ws.item_cap; i += WAVE)
+                sink ^= rmw_xchg(&q.ws.items[(size_t)(first + i) * IW], kVoidItem);
+        } else {
+            for (uint32_t i0 = 0; i0 < n; i0 += IPI) {
+                const uint32_t i = i0 + lane / IW, w = lane % IW;
+                if (lane < IPI * IW && i < n) {
+                    uint32_t val = 0;
+                    bool write = true;
+                    if (i < n_ent) {
+                        const uint32_t ee = ent[i];
+                        const uint32_t rA = ee & REC_MASK, rB = (ee >> REC_BITS) & REC_MASK;
+                        if (w == 0) val = pose;
+                        else if (w == 1) val = rtopo[rA];
+                        else if (w == 2) val = rtopo[rB];
+                        else if (w == 3) val = MODE == MODE_DIST ? __float_as_uint(ent_lb[i]) : 0u;
+                        else if (w < 4 + 2 * K) val = __float_as_uint(rbnd[(size_t)rA * 2 * K + (w - 4)]);
+                        else val = __float_as_uint(rbnd[(size_t)rB * 2 * K + (w - 4 - 2 * K)]);
+                    } else {
+                        const uint32_t j = i - n_ent;
+                        const uint2 le = lq[j];
+                        if (w == 0) val = pose;
+                        else if (w == 1) val = le.x;
+                        else if (w == 2) val = le.y;
+                        else if (w == 3) val = MODE == MODE_DIST ? __float_as_uint(lq_lb[j]) : 0u;
+                        else write = false;  // a leaf pair needs no bounds
+                    }
+                    if (write) sink ^= rmw_xchg(&q.ws.items[(size_t)(first + i) * IW + w], val);
+                }
+            }
+        }
+        wait_mem(sink);
+        for (uint32_t i = lane; i < n && first + i < q.ws.item_cap; i += WAVE) rmw_xchg(&q.ws.ready[first + i], 1u);
+        return ok ? n : 0u;
+    };
+
+    bool poses_left = true;
+    uint32_t cur_pose = 0xFFFFFFFFu;
+    Pose P;
+    float e_abs = 0.0f, e_sph = 0.0f;
+    const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
 
     for (;;) {
-        // ---- next pose ----
-        uint32_t pose;
-        if (pass == 0) {
+        // ---- next work unit: a pose, or once they are gone a donated item ----
+        uint32_t pose = 0;
+        bool from_item = false;
+        uint32_t it_tA = 0, it_tB = 0;
+        float it_lb = 0.0f;
+        if (poses_left) {
             uint32_t p = 0;
             if (lane == 0) p = atomicAdd(&hdr->pose_next, 1u);
             pose = uni(p);
-            if (pose >= q.n_poses) break;
-        } else {
-            uint32_t p = 0;
-            if (lane == 0) p = atomicAdd(&hdr->fallback_next, 1u);
-            p = uni(p);
-            if (p >= uni(*(volatile uint32_t *)&hdr->fallback_count) || p >= q.n_poses) break;
-            pose = uni(q.ws.fallback_list[p]);
+            if (t_first == 0) t_first = wall_clock64();
+            if (pose >= q.n_poses) {
+                poses_left = false;
+                t_drain = wall_clock64();
+            }
         }
-        Pose P;
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-#pragma unroll
-            for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
-            P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
+        if (!poses_left) {
+            if (!can_donate) break;
+            uint32_t slot = 0;
+            if (lane == 0) slot = rmw_add(&hdr->q_head, 1u);
+            slot = uni(slot);
+            // wait until the slot is filled or no work is left anywhere,
+            // backing off so that thousands of waiting waves leave the
+            // memory system to the busy ones
+            const unsigned long long t0 = wall_clock64();
+            uint32_t got = 0;
+            for (uint32_t spin = 0;; spin++) {
+                uint32_t r = 0, pend = 1;
+                if (lane == 0) {
+                    if (slot < q.ws.item_cap) r = rmw_read(&q.ws.ready[slot]);
+                    if (!r && (spin & 3) == 3) pend = rmw_read(&hdr->pending);
+                }
+                if (uni(r)) {
+                    got = 1;
+                    break;
+                }
+                if (uni(pend) == 0) break;
+                if (wall_clock64() - t0 > kWaitLimit) {
+                    if (lane == 0) rmw_xchg(&hdr->error, 1u);
+                    break;
+                }
+                if (spin < 4) __builtin_amdgcn_s_sleep(8);
+                else if (spin < 16) __builtin_amdgcn_s_sleep(32);
+                else __builtin_amdgcn_s_sleep(96);
+            }
+            if (!got) break;
+            uint32_t v = 0;
+            if (lane < IW) v = rmw_read(&q.ws.items[(size_t)slot * IW + lane]);
+            pose = lane_of(v, 0);
+            if (pose == kVoidItem) continue;  // a slot of a donation that found the queue full
+            it_tA = lane_of(v, 1);
+            it_tB = lane_of(v, 2);
+            it_lb = __uint_as_float(lane_of(v, 3));
+            if (lane >= 4 && lane < IW) rbnd[lane - 4] = __uint_as_float(v);
+            from_item = true;
+            if (MODE == MODE_BOOL) {
+                uint32_t decided = 0;
+                if (lane == 0) decided = rmw_read(&q.ws.hitw[pose]);
+                if (uni(decided)) {  // another unit of this pose already found a collision
+                    if (lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
+                    continue;
+                }
+            }
         }
-        pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, coef, upidx, vtU, vtL, lane);
-        // distance: FP32 leaf-distance error bound e (generous multiple of
-        // the transform and closest-point rounding at this coordinate scale)
-        const float tnorm = sqrtf(P.t[0] * P.t[0] + P.t[1] * P.t[1] + P.t[2] * P.t[2]);
-        const float e_abs = 256.0f * 0x1p-24f * (tnorm + 3.5f * (MA.max_abs + MB.max_abs));
-        const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
-        // absolute rounding allowance of the sphere bound below
-        const float e_sph = 64.0f * 0x1p-24f *
-                            (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
+        if (pose != cur_pose) {
+            cur_pose = pose;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+#pragma unroll
+                for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
+                P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
+            }
+            pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, coef, upidx, vtU, vtL, lane);
+            // distance: FP32 leaf-distance error bound (a generous multiple of the
+            // transform and closest-point rounding at this coordinate scale), and
+            // the absolute rounding allowance of the sphere bound
+            const float tnorm = sqrtf(P.t[0] * P.t[0] + P.t[1] * P.t[1] + P.t[2] * P.t[2]);
+            e_abs = 256.0f * 0x1p-24f * (tnorm + 3.5f * (MA.max_abs + MB.max_abs));
+            e_sph = 64.0f * 0x1p-24f *
+                    (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
+        }
 
-        // ---- root frame: record 0 = A's root, record 1 = B's root ----
-        if (lane < 2) {
-            const DevModel &M = lane == 0 ? MA : MB;
-            uint32_t tw = M.topo[0];
-            float bnd[2 * K];
-            decode_node<K, BITS>(M, 0, tw, (const float *)nullptr, bnd);
-            rtopo[lane] = tw;
+        // ---- initial state ----
+        uint32_t f_id = 0, f_base = 0, f_nA = 1, f_total_tasks = 1;
+        uint32_t s_aoff[EMAX] = {0, 0, 0, 0};
+        uint32_t s_boff[EMAX] = {1, 0, 0, 0}, s_nb[EMAX] = {1, 0, 0, 0};
+        uint32_t s_tpre[EMAX + 1] = {0, 64, 64, 64, 64};
+        bool have_frame;
+        uint32_t top = 0, lq_count = 0;
+        bool hit = false, overflow = false, pair_overflow = false;
+        // shared: other units of this pose may exist, so the per-pose answer
+        // in device memory is read and merged while traversing
+        bool shared = from_item;
+        float best32 = INFINITY;
+        double best64 = INFINITY;
+        uint32_t next_look = kDonatePeriod, next_sync = kSyncPeriod;
+        if (!from_item) {
+            // root frame: record 0 = A's root, record 1 = B's root; the root pair is tested first
+            if (lane < 2) {
+                const DevModel &M = lane == 0 ? MA : MB;
+                uint32_t tw = M.topo[0];
+                float bnd[2 * K];
+                decode_node<K, BITS>(M, 0, tw, (const float *)nullptr, bnd);
+                rtopo[lane] = tw;
 #pragma unroll
-            for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
+                for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
+            }
+            have_frame = true;
+        } else {
+            // the item's pair already passed its BV test: records 0 and 1 hold it
+            if (lane == 0) {
+                rtopo[0] = it_tA;
+                rtopo[1] = it_tB;
+            }
+            if (topo_leaf(it_tA) && topo_leaf(it_tB)) {
+                if (lane == 0) {
+                    lq[0] = make_uint2(it_tA, it_tB);
+                    if (MODE == MODE_DIST) lq_lb[0] = it_lb;
+                }
+                lq_count = 1;
+            } else {
+                if (lane == 0) {
+                    ent[0] = 0u | (1u << REC_BITS);
+                    if (MODE == MODE_DIST) ent_lb[0] = it_lb;
+                }
+                top = 1;
+            }
+            if (MODE == MODE_DIST) {
+                uint32_t g = 0;
+                if (lane == 0) g = rmw_read(&q.ws.best32[pose]);
+                best32 = __uint_as_float(uni(g));
+            }
+            have_frame = false;
         }
         if (lane == 0) frame_end[0] = 2;
         wave_sync();
 
-        // current frame description (wave-uniform)
-        uint32_t f_id = 0, f_base = 0, f_nslots = 1, f_nA = 1, f_total_tasks = 1;
-        uint32_t s_aoff[EMAX] = {0, 0, 0, 0}, s_na[EMAX] = {1, 0, 0, 0};
-        uint32_t s_boff[EMAX] = {1, 0, 0, 0}, s_nb[EMAX] = {1, 0, 0, 0};
-        uint32_t s_tpre[EMAX + 1] = {0, 64, 64, 64, 64};
-        bool have_frame = true;
-        uint32_t top = 0, lq_count = 0;
-        bool hit = false, overflow = false, pair_overflow = false;
-        float best32 = INFINITY;
-        double best64 = INFINITY;
-
+        uint32_t steps = 0;
         for (;;) {
+            steps++;
             if (have_frame) {
                 have_frame = false;
                 // -------- transform A's records of the frame into B's frame --------
@@ -450,7 +647,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
                 uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
                 if (lq_count + n_ll > lim.leafq || top + n_nd > lim.entries) {
-                    overflow = true;
+                    overflow = true;  // cannot happen: node steps check the room first
                     break;
                 }
                 if (survive && ll) {
@@ -487,6 +684,20 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             }
             if (MODE == MODE_BOOL && hit) break;
             if (MODE == MODE_DIST && best64 == 0.0) break;
+
+            // -------- shared answer of the pose: stop or tighten --------
+            if (shared && steps >= next_sync) {
+                next_sync = steps + kSyncPeriod;
+                if (MODE == MODE_BOOL) {
+                    uint32_t d = 0;
+                    if (lane == 0) d = rmw_read(&q.ws.hitw[pose]);
+                    if (uni(d)) break;
+                } else if (MODE == MODE_DIST) {
+                    uint32_t g = 0;
+                    if (lane == 0) g = rmw_read(&q.ws.best32[pose]);
+                    best32 = fminf(best32, __uint_as_float(uni(g)));
+                }
+            }
 
             // -------- leaf step --------
             uint32_t trig = lq_trigger_full < 1 ? 1 : lq_trigger_full;
@@ -564,7 +775,13 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     bool h = active && (res == 1 || res == 3);
                     cnt.tri_fp64 += __popcll(__ballot(active && res >= 3));
                     uint64_t mh = __ballot(h);
-                    if (mh) hit = true;
+                    if (mh) {
+                        hit = true;
+                        if (lane == 0) {
+                            q.hit[pose] = 1;
+                            if (MODE == MODE_BOOL && shared) rmw_xchg(&q.ws.hitw[pose], 1u);
+                        }
+                    }
                     if (MODE == MODE_PAIRS && mh) {
                         uint32_t nh = __popcll(mh);
                         uint32_t b0 = 0;
@@ -573,13 +790,19 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                         if (h) {
                             uint32_t idx = b0 + mbcnt(mh);
                             if (idx < q.pair_cap)
-                                q.ws.pair_raw[idx] = make_uint4(pose | ((uint32_t)pass << 31), MA.perm[triA], MB.perm[triB], 0u);
+                                q.ws.pair_raw[idx] = make_uint4(pose, MA.perm[triA], MB.perm[triB], 0u);
                         }
                         if (b0 + nh > q.pair_cap) pair_overflow = true;
                     }
                 } else {
                     float d32 = active ? __int_as_float(res) : INFINITY;
-                    best32 = fminf(best32, wave_min(d32));
+                    float wmin = wave_min(d32);
+                    if (wmin < best32) {
+                        best32 = wmin;
+                        if (shared && lane == 0)
+                            __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best32), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
                     const float tau2 = add_up(best32, 2.0f * e_abs);
                     bool refine = active && d32 <= tau2;
                     cnt.tri_fp64 += __popcll(__ballot(refine));
@@ -612,7 +835,41 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             }
             if (top == 0) break;
 
-            // -------- node step: pop a batch of entries, decode their children --------
+            // -------- feed waiting waves with the bottom of the stack --------
+            if (can_donate && top >= 2 && steps >= next_look) {
+                next_look = steps + kDonatePeriod;
+                uint32_t want = 0;
+                if (lane == 0) {
+                    unsigned long long ht = rmw_read64((unsigned long long *)&hdr->q_head);
+                    uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
+                    want = h > t ? min(h - t, min(top / 2, kMaxDonate)) : 0u;
+                }
+                want = uni(want);
+                if (want && publish(pose, want, want, best32) == want) {
+                    cnt.donated += want;
+                    shared = true;
+                    // the remaining entries move down (their records stay put)
+                    const uint32_t rem = top - want;
+                    for (uint32_t b0 = 0; b0 < rem; b0 += WAVE) {
+                        const uint32_t i = b0 + lane;
+                        uint32_t ev = 0;
+                        float lv = 0.0f;
+                        if (i < rem) {
+                            ev = ent[want + i];
+                            if (MODE == MODE_DIST) lv = ent_lb[want + i];
+                        }
+                        wave_sync();
+                        if (i < rem) {
+                            ent[i] = ev;
+                            if (MODE == MODE_DIST) ent_lb[i] = lv;
+                        }
+                        wave_sync();
+                    }
+                    top = rem;
+                }
+            }
+
+            // -------- node step: choose a batch of entries whose tests fit one wave --------
             const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
             uint32_t my_e = 0, my_na = 0, my_nb = 0, my_tasks = 0, my_pA = 0, my_pB = 0;
             if (lane < (uint32_t)EMAX && lane < top) {
@@ -625,7 +882,6 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 my_tasks = my_na * my_nb;
                 if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_tasks = my_na = my_nb = 0;
             }
-            // greedy prefix of at most EMAX entries whose tests fit in one wave
             uint32_t n_pop = 0, acc = 0;
             uint32_t e_s[EMAX], na_s[EMAX], nb_s[EMAX], pA_s[EMAX], pB_s[EMAX];
 #pragma unroll
@@ -645,7 +901,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     acc += tk;
                 }
             }
-            // new frame sits on top of the frame of the next remaining entry
+            // the new frame sits on top of the frame of the next remaining entry
             uint32_t remaining = top - n_pop;
             uint32_t new_id = 0, new_base = 0;
             if (remaining > 0) {
@@ -684,14 +940,25 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     accb += n_nb[d];
                 }
             }
-            top = remaining;
-            if (ns == 0) continue;  // every popped entry was culled
-            uint32_t total_rec = nA_tot + nB_tot;
-            if (new_id >= (uint32_t)MAX_FRAMES || new_base + total_rec > lim.records ||
-                new_base + total_rec > REC_MASK + 1u) {
-                overflow = true;
+            const uint32_t total_rec = nA_tot + nB_tot;
+            // room for the new frame and for every possible survivor?
+            const bool fits = new_id < (uint32_t)MAX_FRAMES && new_base + total_rec <= lim.records &&
+                              new_base + total_rec <= REC_MASK + 1u && remaining + tasks_tot <= lim.entries;
+            if (!fits) {
+                // hand every pending pair (node pairs with their decoded
+                // bounds, and queued leaf pairs) to the item queue; the
+                // unit ends here
+                const uint32_t n_items = top + lq_count;
+                if (can_donate && publish(pose, n_items, top, best32) == n_items) {
+                    cnt.donated += n_items;
+                    shared = true;
+                } else {
+                    overflow = true;
+                }
                 break;
             }
+            top = remaining;
+            if (ns == 0) continue;  // every popped entry was culled
             // decode: one lane per new record (register staging: the new
             // frame may overwrite the popped entries' own frames)
             uint32_t my_topo = 0;
@@ -732,7 +999,6 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 for (int k = 0; k < 2 * K; k++) rbnd[(size_t)(new_base + lane) * 2 * K + k] = my_b[k];
             }
             if (lane == 0) frame_end[new_id] = new_base + total_rec;
-            // counters: children fetched by the expanded sides
             {
                 unsigned long long nbytes = 0;
 #pragma unroll
@@ -753,46 +1019,33 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             // the new frame becomes the current one
             f_id = new_id;
             f_base = new_base;
-            f_nslots = ns;
             f_nA = nA_tot;
             f_total_tasks = tasks_tot;
 #pragma unroll
             for (int d = 0; d < EMAX; d++) {
                 s_aoff[d] = n_aoff[d];
-                s_na[d] = n_na[d];
                 s_boff[d] = n_boff[d];
                 s_nb[d] = n_nb[d];
-                s_tpre[d] = n_tpre[d];
+                s_tpre[d] = (uint32_t)d < ns ? n_tpre[d] : 64u;
             }
             s_tpre[EMAX] = 64;
-            // slots past the last one never match a lane
-#pragma unroll
-            for (int d = 1; d < EMAX; d++)
-                if ((uint32_t)d >= ns) s_tpre[d] = 64;
-            (void)f_nslots;
             have_frame = true;
         }
+        cnt.max_steps = max(cnt.max_steps, steps);
 
-        // ---- outputs for this pose ----
+        // ---- results of this unit ----
         if (lane == 0) {
-            uint8_t st = 0;
-            if (overflow) {
-                if (pass == 0 && !q.no_fallback) {
-                    uint32_t slot = atomicAdd(&hdr->fallback_count, 1u);
-                    q.ws.fallback_list[slot] = pose;
-                    q.ws.fell_back[pose] = 1;
-                    st = 0xFF;  // resolved by the fallback pass
-                } else {
-                    st = 1;  // CBVH_POSE_STACK_OVERFLOW
-                }
-            } else if (pair_overflow) {
-                st = 2;  // CBVH_POSE_PAIR_OVERFLOW
+            if (overflow) q.status[pose] = 1;            // CBVH_POSE_STACK_OVERFLOW
+            else if (pair_overflow) q.status[pose] = 2;  // CBVH_POSE_PAIR_OVERFLOW
+            if (MODE == MODE_DIST) {
+                if (best32 < INFINITY)
+                    __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best32), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                if (best64 < INFINITY)
+                    __hip_atomic_fetch_min(&q.ws.best64[pose], (unsigned long long)__double_as_longlong(best64),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (st != 0xFF) {
-                q.status[pose] = st;
-                if (MODE != MODE_DIST) q.hit[pose] = hit ? 1 : 0;
-                else q.dist[pose] = (float)best64;
-            }
+            if (can_donate) rmw_add(&hdr->pending, 0xFFFFFFFFu);  // this unit is finished
         }
         wave_sync();
     }
@@ -804,24 +1057,38 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         atomicAdd(&hdr->counters[C_EXPANSIONS], cnt.expansions);
         atomicAdd(&hdr->counters[C_NODE_BYTES], cnt.node_bytes);
         atomicAdd(&hdr->counters[C_TRI_BYTES], cnt.tri_bytes);
+        atomicAdd(&hdr->counters[C_DONATED], cnt.donated);
         atomicMax(&hdr->counters[C_MAX_ENTRIES], (unsigned long long)cnt.max_entries);
         atomicMax(&hdr->counters[C_MAX_RECORDS], (unsigned long long)cnt.max_records);
-        if (pass == 1) {
-            uint32_t fb = *(volatile uint32_t *)&hdr->fallback_count;
-            if (blockIdx.x == 0) atomicAdd(&hdr->counters[C_FALLBACK_POSES], (unsigned long long)fb);
-        }
+        atomicMax(&hdr->counters[C_MAX_POSE_STEPS], (unsigned long long)cnt.max_steps);
+        if (t_first) atomicMin(&hdr->counters[C_T_START], t_first);
+        atomicMin(&hdr->counters[C_T_DRAIN], t_drain);
+        atomicMax(&hdr->counters[C_T_END], (unsigned long long)wall_clock64());
     }
 }
-
 // ---------------------------------------------------------------------------
-// workspace init and pair-list finalize
+// workspace init, distance output, pair-list finalize
 // ---------------------------------------------------------------------------
-__global__ void init_kernel(WsHeader *hdr, uint8_t *fell_back, uint32_t *pair_cnt, uint32_t *pair_cursor, uint32_t n)
+__global__ void init_kernel(WsHeader *hdr, uint8_t *hit, uint8_t *status, unsigned int *best32,
+                            unsigned long long *best64, uint32_t *pair_cnt, uint32_t *pair_cursor, uint32_t *hitw,
+                            uint32_t *ready, uint32_t n_ready, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < sizeof(WsHeader) / 4) ((uint32_t *)hdr)[i] = 0u;
+    if (i < sizeof(WsHeader) / 4) {
+        bool is_min = i / 2 == C_T_START || i / 2 == C_T_DRAIN;  // 64-bit counters that take minima
+        uint32_t v = is_min ? 0xFFFFFFFFu : 0u;
+        if (i == offsetof(WsHeader, pending) / 4) v = n;  // every pose is pending
+        ((uint32_t *)hdr)[i] = v;
+    }
+    if (i < n_ready) ready[i] = 0;
     if (i < n) {
-        fell_back[i] = 0;
+        status[i] = 0;
+        if (hit) hit[i] = 0;
+        if (hitw) hitw[i] = 0;
+        if (best32) {
+            best32[i] = 0x7F800000u;                 // +inf
+            best64[i] = 0x7FF0000000000000ull;       // +inf
+        }
         if (pair_cnt) {
             pair_cnt[i] = 0;
             pair_cursor[i] = 0;
@@ -829,20 +1096,17 @@ __global__ void init_kernel(WsHeader *hdr, uint8_t *fell_back, uint32_t *pair_cn
     }
 }
 
-__device__ __forceinline__ bool pair_valid(const uint4 &r, const uint8_t *fell_back)
+__global__ void dist_out_kernel(const unsigned long long *best64, float *dist, uint32_t n)
 {
-    uint32_t pose = r.x & 0x7FFFFFFFu, pass = r.x >> 31;
-    return pass == 1 || !fell_back[pose];
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dist[i] = (float)__longlong_as_double((long long)best64[i]);
 }
 
-__global__ void pair_count_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, const uint8_t *fell_back,
-                                  uint32_t *cnt)
+__global__ void pair_count_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, uint32_t *cnt)
 {
     uint32_t total = min(hdr->pair_count, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        uint4 r = raw[i];
-        if (pair_valid(r, fell_back)) atomicAdd(&cnt[r.x & 0x7FFFFFFFu], 1u);
-    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x)
+        atomicAdd(&cnt[raw[i].x], 1u);
 }
 
 // exclusive scan of n counts by one workgroup of 1024 threads
@@ -871,15 +1135,13 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const uint32_t *cnt, ui
     if (threadIdx.x == 0) offsets[n] = carry;
 }
 
-__global__ void pair_scatter_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, const uint8_t *fell_back,
-                                    const uint32_t *offsets, uint32_t *cursor, unsigned long long *keys)
+__global__ void pair_scatter_kernel(const WsHeader *hdr, const uint4 *raw, uint32_t cap, const uint32_t *offsets,
+                                    uint32_t *cursor, unsigned long long *keys)
 {
     uint32_t total = min(hdr->pair_count, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         uint4 r = raw[i];
-        if (!pair_valid(r, fell_back)) continue;
-        uint32_t pose = r.x & 0x7FFFFFFFu;
-        uint32_t pos = offsets[pose] + atomicAdd(&cursor[pose], 1u);
+        uint32_t pos = offsets[r.x] + atomicAdd(&cursor[r.x], 1u);
         keys[pos] = ((unsigned long long)r.y << 32) | r.z;
     }
 }
@@ -897,8 +1159,7 @@ __global__ __launch_bounds__(256) void pair_sort_kernel(const uint32_t *offsets,
         uint32_t p2 = 1;
         while (p2 < len) p2 <<= 1;
         unsigned long long *arr = keys + b;
-        bool in_lds = p2 <= SORT_LDS;
-        if (in_lds) {
+        if (p2 <= SORT_LDS) {
             for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) sk[i] = i < len ? arr[i] : ~0ull;
             __syncthreads();
             for (uint32_t k = 2; k <= p2; k <<= 1)
@@ -979,101 +1240,107 @@ __global__ void decode_all_kernel(DevModel M, float *out)
     }
 }
 
-template <int K, int BITS, int MODE>
-hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+// Launch shape knob (for the tuner; default when unset or 0): CBVH_WAVES_PER_CU.
+uint32_t env_u32(const char *name, uint32_t dflt)
 {
-    if (pass == 0) {
-        Layout L = make_layout(K, MODE, lim);
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cus < 1) cus = 256;
-        uint32_t per_cu = (uint32_t)(160u * 1024u / (L.total + 256u));
-        if (per_cu < 1) per_cu = 1;
-        if (per_cu > 32) per_cu = 32;
-        uint32_t grid = (uint32_t)cus * per_cu;
-        if (grid > q.n_poses) grid = q.n_poses;
-        if (grid < 1) grid = 1;
-        hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE, false>), dim3(grid), dim3(WAVE), L.total, s, q, lim, 0);
-    } else {
-        StackLimits gl = fallback_limits(K);
-        hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE, true>), dim3(q.ws.garena_waves), dim3(WAVE), 0, s, q, gl, 1);
-    }
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    unsigned long x = strtoul(v, nullptr, 10);
+    return x ? (uint32_t)x : dflt;
+}
+
+// waves per CU when the LDS state allows it (measured best for the
+// collision workloads: fewer leave latency uncovered, more thrash L2)
+constexpr uint32_t kWavesPerCu = 9;
+
+template <int K, int BITS, int MODE>
+hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
+{
+    Layout L = make_layout(K, MODE, lim);
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 256;
+    uint32_t per_cu = (uint32_t)(160u * 1024u / (L.total + 256u));
+    per_cu = min(per_cu, env_u32("CBVH_WAVES_PER_CU", kWavesPerCu));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 32) per_cu = 32;
+    uint32_t grid = (uint32_t)cus * per_cu;
+    // without donation a wave beyond the pose count has nothing to do
+    if (q.no_split && grid > q.n_poses) grid = q.n_poses;
+    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, q, lim);
     return hipGetLastError();
 }
 
 template <int K, int BITS>
-hipError_t launch_mode(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+hipError_t launch_mode(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
     switch (q.mode) {
-    case MODE_BOOL: return launch_traverse<K, BITS, MODE_BOOL>(q, lim, s, pass);
-    case MODE_PAIRS: return launch_traverse<K, BITS, MODE_PAIRS>(q, lim, s, pass);
-    default: return launch_traverse<K, BITS, MODE_DIST>(q, lim, s, pass);
+    case MODE_BOOL: return launch_traverse<K, BITS, MODE_BOOL>(q, lim, s);
+    case MODE_PAIRS: return launch_traverse<K, BITS, MODE_PAIRS>(q, lim, s);
+    default: return launch_traverse<K, BITS, MODE_DIST>(q, lim, s);
     }
 }
 
-hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s, int pass)
+hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
     uint32_t K = q.A.K, bits = q.A.bits;
     if (K == 3) {
-        if (bits == 0) return launch_mode<3, 0>(q, lim, s, pass);
-        if (bits == 8) return launch_mode<3, 8>(q, lim, s, pass);
-        return launch_mode<3, 16>(q, lim, s, pass);
+        if (bits == 0) return launch_mode<3, 0>(q, lim, s);
+        if (bits == 8) return launch_mode<3, 8>(q, lim, s);
+        return launch_mode<3, 16>(q, lim, s);
     }
-    if (bits == 0) return launch_mode<9, 0>(q, lim, s, pass);
-    if (bits == 8) return launch_mode<9, 8>(q, lim, s, pass);
-    return launch_mode<9, 16>(q, lim, s, pass);
+    if (bits == 0) return launch_mode<9, 0>(q, lim, s);
+    if (bits == 8) return launch_mode<9, 8>(q, lim, s);
+    return launch_mode<9, 16>(q, lim, s);
 }
 
 }  // namespace
 
 size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return make_layout(K, mode, lim).total; }
 
-StackLimits default_limits(uint32_t K)
+StackLimits default_limits(uint32_t K, int mode)
 {
-    if (K == 9) return StackLimits{128, 512, 128};
-    return StackLimits{256, 768, 128};
+    // branch-and-bound keeps many more pairs pending than collision queries
+    if (mode == MODE_DIST) return K == 9 ? StackLimits{160, 512, 128} : StackLimits{256, 768, 128};
+    return K == 9 ? StackLimits{80, 192, 128} : StackLimits{160, 384, 128};
 }
 
-StackLimits fallback_limits(uint32_t K)
-{
-    (void)K;
-    return StackLimits{4096, 8192, 128};
-}
-
-uint32_t fallback_waves() { return 128; }
+uint32_t item_words(uint32_t K) { return words_of_item(K); }
 
 hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t s, uint32_t *pair_out,
                         uint32_t *pair_offsets)
 {
     const uint32_t n = q.n_poses;
+    const bool dist = q.mode == MODE_DIST, pairs = q.mode == MODE_PAIRS;
     {
-        uint32_t threads = 256, items = n > 96 ? n : 96;
+        // the item queue's ready flags start clear (its slots are numbered
+        // from 0 in every query)
+        const uint32_t n_ready = q.no_split ? 0u : q.ws.item_cap;
+        uint32_t threads = 256, items = max(max(n, n_ready), (uint32_t)(sizeof(WsHeader) / 4));
         hipLaunchKernelGGL(init_kernel, dim3((items + threads - 1) / threads), dim3(threads), 0, s, q.ws.hdr,
-                           q.ws.fell_back, q.mode == MODE_PAIRS ? q.ws.pair_cnt : nullptr,
-                           q.mode == MODE_PAIRS ? q.ws.pair_cursor : nullptr, n);
+                           dist ? nullptr : q.hit, q.status, dist ? q.ws.best32 : nullptr,
+                           dist ? q.ws.best64 : nullptr, pairs ? q.ws.pair_cnt : nullptr,
+                           pairs ? q.ws.pair_cursor : nullptr, q.mode == MODE_BOOL ? q.ws.hitw : nullptr, q.ws.ready,
+                           n_ready, n);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_any(q, lim, s, 0);
+    hipError_t e = launch_any(q, lim, s);
     if (e != hipSuccess) return e;
-    if (!q.no_fallback) {
-        e = launch_any(q, lim, s, 1);
-        if (e != hipSuccess) return e;
-    }
-    if (q.mode == MODE_PAIRS) {
+    if (dist) {
+        hipLaunchKernelGGL(dist_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, q.ws.best64, q.dist, n);
+    } else if (pairs) {
         hipLaunchKernelGGL(pair_count_kernel, dim3(256), dim3(256), 0, s, q.ws.hdr, q.ws.pair_raw, q.pair_cap,
-                           q.ws.fell_back, q.ws.pair_cnt);
+                           q.ws.pair_cnt);
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, s, q.ws.pair_cnt, pair_offsets, n);
         hipLaunchKernelGGL(pair_scatter_kernel, dim3(256), dim3(256), 0, s, q.ws.hdr, q.ws.pair_raw, q.pair_cap,
-                           q.ws.fell_back, pair_offsets, q.ws.pair_cursor, q.ws.pair_keys);
+                           pair_offsets, q.ws.pair_cursor, q.ws.pair_keys);
         uint32_t g = n < 2048 ? n : 2048;
         if (g < 1) g = 1;
         hipLaunchKernelGGL(pair_sort_kernel, dim3(g), dim3(256), 0, s, pair_offsets, q.ws.pair_keys, pair_out, n);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 hipError_t launch_decode_all(const DevModel &m, float *out, hipStream_t s)

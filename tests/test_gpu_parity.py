@@ -211,29 +211,46 @@ def test_single_triangle_meshes():
     assert oracle.collide(A, B, up)[0] and not oracle.collide(A, B, lift)[0]
 
 
-def test_forced_stack_overflow_falls_back_to_the_global_stack():
+def test_small_stacks_donate_work_and_keep_answers_exact():
     P, _ = W.config0_poses()
     A, B = W.oracle_meshes(0)
     ma, mb = models(0)
     Pd = torch.from_numpy(P).to(DEV)
     try:
-        cb.cbvh_set_stack_limits(entries=6, records=12)
+        cb.cbvh_set_stack_limits(entries=128, records=96)
         ws = cb.workspace(ma, mb, len(P), cb.PAIRS, 1 << 18)
         hit, st, pairs, offs = cb.collide(ma, mb, Pd, flags=cb.PAIRS, pair_capacity=1 << 18, ws=ws)
         stats = cb.cbvh_stats(ws.buf)
-        hit2, st2 = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT | cb.NO_FALLBACK)
+        ws2 = cb.workspace(ma, mb, len(P))
+        hit2, st2 = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT, ws=ws2)
+        hit3, st3 = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT | cb.NO_SPLIT)
     finally:
         cb.cbvh_set_stack_limits(0, 0)
-    assert stats["fallback_poses"] > 0
+    _log(f"small stacks: {stats}")
+    assert stats["donated_items"] > 0
     st, pairs, offs = st.cpu().numpy(), pairs.cpu().numpy(), offs.cpu().numpy()
     assert (st == 0).all()
     for i, p in enumerate(P):
         assert np.array_equal(pairs[offs[i]:offs[i + 1], 1:].astype(np.uint32), oracle.collide_pairs(A, B, p))
-    st2 = st2.cpu().numpy()
-    assert (st2 == cb.POSE_STACK_OVERFLOW).any()
     ref, _ = oracle.collide_batch(A, B, P)
-    ok = st2 == 0
-    assert np.array_equal(hit2.cpu().numpy()[ok].astype(bool), ref[ok])
+    assert (st2.cpu().numpy() == 0).all()
+    assert np.array_equal(hit2.cpu().numpy().astype(bool), ref)
+    # without donation, poses that outgrow the small stacks are flagged; the others stay exact
+    st3 = st3.cpu().numpy()
+    ok = st3 == 0
+    assert np.array_equal(hit3.cpu().numpy()[ok].astype(bool), ref[ok])
+    assert set(np.unique(st3)) <= {0, cb.POSE_STACK_OVERFLOW}
+
+
+def test_split_and_unsplit_runs_agree():
+    w = configs.WORKLOADS[2]
+    P = torch.from_numpy(w.raw_poses(512)).to(DEV)
+    ma, mb = models(2)
+    d1, s1 = cb.distance(ma, mb, P)
+    d2, s2 = cb.distance(ma, mb, P, flags=cb.NO_SPLIT)
+    ok = (s1.cpu().numpy() == 0) & (s2.cpu().numpy() == 0)
+    assert ok.mean() > 0.99
+    assert np.array_equal(d1.cpu().numpy()[ok].view(np.uint32), d2.cpu().numpy()[ok].view(np.uint32))
 
 
 def test_pair_buffer_overflow_is_flagged_per_pose():
