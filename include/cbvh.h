@@ -119,6 +119,7 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 #define CBVH_POSE_OK 0u
 #define CBVH_POSE_STACK_OVERFLOW 1u /* traversal state exhausted and no room to donate it; results invalid */
 #define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
+#define CBVH_POSE_FP64_OVERFLOW 3u  /* workspace buffer of leaf pairs for FP64 re-evaluation full; results invalid */
 
 /* Workspace bytes (device, caller-owned, 256-byte aligned) for a query on
  * models a and b with n poses. */
@@ -168,7 +169,7 @@ cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, 
 typedef struct {
     uint64_t bv_tests;       /* BV-pair overlap / lower-bound evaluations (Algorithm 1 "intersect") */
     uint64_t tri_tests;      /* triangle-pair tests (FP32) */
-    uint64_t tri_fp64;       /* triangle-pair tests re-decided or refined in FP64 */
+    uint64_t tri_fp64;       /* triangle pairs handed to the FP64 stage (undecided in FP32, or distance candidates) */
     uint64_t expansions;     /* node-pair expansions (children fetched and decoded) */
     uint64_t node_bytes;     /* descriptor + topology bytes the expansions fetched */
     uint64_t tri_bytes;      /* triangle bytes the leaf tests fetched */

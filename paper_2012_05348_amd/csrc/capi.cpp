@@ -67,8 +67,8 @@ cbvh::StackLimits current_limits(uint32_t K, int mode)
 
 // workspace carving: [header | item queue | per-pose answers | pair buffers]
 struct WsPlan {
-    uint64_t hdr, items, ready, hitw, best32, best64, pair_raw, pair_cnt, pair_cursor, pair_keys, total;
-    uint32_t item_cap, item_words;
+    uint64_t hdr, items, ready, hitw, fix, best32, best64, pair_raw, pair_cnt, pair_cursor, pair_keys, total;
+    uint32_t item_cap, item_words, fix_cap;
 };
 
 WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
@@ -91,6 +91,13 @@ WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
     p.items = take((uint64_t)p.item_cap * p.item_words * 4ull);
     p.ready = take(4ull * p.item_cap);
     p.hitw = take(mode == cbvh::MODE_BOOL ? 4ull * n : 0);
+    // leaf pairs for the FP64 stage: undecided intersections are rare;
+    // distance candidates (within 2 e of a running minimum) number about a
+    // hundred per pose on near-contact workloads
+    uint64_t fcap = dist ? 256ull * n + (1ull << 20) : n + 65536ull;
+    if (fcap > (1ull << 26)) fcap = 1ull << 26;
+    p.fix_cap = (uint32_t)fcap;
+    p.fix = take(16ull * p.fix_cap);
     p.best32 = take(dist ? 4ull * n : 0);
     p.best64 = take(dist ? 8ull * n : 0);
     p.pair_raw = take(pairs ? 16ull * pair_cap : 0);
@@ -151,6 +158,8 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.ws.item_cap = plan.item_cap;
     q.ws.item_words = plan.item_words;
     q.ws.hitw = (uint32_t *)(w + plan.hitw);
+    q.ws.fix = (uint4 *)(w + plan.fix);
+    q.ws.fix_cap = plan.fix_cap;
     q.ws.best32 = (unsigned int *)(w + plan.best32);
     q.ws.best64 = (unsigned long long *)(w + plan.best64);
     q.ws.pair_raw = (uint4 *)(w + plan.pair_raw);

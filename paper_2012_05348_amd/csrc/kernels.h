@@ -48,7 +48,8 @@ struct WsHeader {
     uint32_t pose_next;   // persistent-wave pose queue
     uint32_t pair_count;  // pairs appended (may exceed capacity)
     uint32_t error;       // a wave gave up waiting for an item (never expected)
-    uint32_t pad0[29];
+    uint32_t fix_count;   // leaf pairs handed to the FP64 stage (may exceed capacity)
+    uint32_t pad0[28];
     uint32_t q_head;      // next item slot to claim (8-byte aligned: read together with q_tail)
     uint32_t q_tail;      // next item slot to reserve
     uint32_t pad1[30];
@@ -71,6 +72,8 @@ struct Workspace {
     uint32_t item_cap;        // item slots (slot indices are never reused within a query)
     uint32_t item_words;      // dwords per item
     uint32_t *hitw;           // [n] collision found (read and written with atomics)
+    uint4 *fix;               // [fix_cap] (pose, triA, triB, FP32 distance bits) for the FP64 stage
+    uint32_t fix_cap;
     unsigned int *best32;     // [n] distance: FP32 bits of the best leaf distance so far
     unsigned long long *best64;  // [n] distance: FP64 bits of the best refined distance
     uint4 *pair_raw;          // [pair_capacity] (pose, triA, triB, 0)

@@ -271,6 +271,16 @@ __device__ __forceinline__ V3<double> xform_f64(const Pose &P, V3<float> x)
 }
 __device__ __forceinline__ V3<double> to64(V3<float> x) { return {(double)x.x, (double)x.y, (double)x.z}; }
 
+// Distance queries: bound on the error of an FP32 leaf distance (a generous
+// multiple of the transform and closest-point rounding at this coordinate
+// scale).  The traversal and the FP64 stage evaluate it identically.
+__device__ __forceinline__ float dist_err_abs(const float *pose, float maxA, float maxB)
+{
+    const float tx = pose[3], ty = pose[7], tz = pose[11];
+    const float tnorm = sqrtf(tx * tx + ty * ty + tz * tz);
+    return 256.0f * 0x1p-24f * (tnorm + 3.5f * (maxA + maxB));
+}
+
 // 16-bit reciprocal for n in [1, 8]: (x * r) >> 16 == x / n for x < 64
 __device__ __forceinline__ uint32_t recip16(uint32_t n) { return (65536u + n - 1u) / n; }
 
@@ -297,9 +307,13 @@ __device__ __forceinline__ uint32_t rmw_xchg(uint32_t *p, uint32_t v)
 {
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned long long rmw_read64(unsigned long long *p)
+// Polling reads are device-scope atomic loads: coherent like the RMWs but
+// served without the per-address serialization of RMWs, which thousands of
+// waves polling one word would otherwise queue behind.
+__device__ __forceinline__ uint32_t poll(uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ unsigned long long poll64(unsigned long long *p)
 {
-    return __hip_atomic_fetch_add(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Wait until this lane's memory operations have completed.  `dep` carries
 // the results of the atomics to wait for, so they are issued in their
@@ -454,8 +468,8 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             for (uint32_t spin = 0;; spin++) {
                 uint32_t r = 0, pend = 1;
                 if (lane == 0) {
-                    if (slot < q.ws.item_cap) r = rmw_read(&q.ws.ready[slot]);
-                    if (!r && (spin & 3) == 3) pend = rmw_read(&hdr->pending);
+                    if (slot < q.ws.item_cap) r = poll(&q.ws.ready[slot]);
+                    if (!r && (spin & 7) == 7) pend = poll(&hdr->pending);
                 }
                 if (uni(r)) {
                     got = 1;
@@ -482,7 +496,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             from_item = true;
             if (MODE == MODE_BOOL) {
                 uint32_t decided = 0;
-                if (lane == 0) decided = rmw_read(&q.ws.hitw[pose]);
+                if (lane == 0) decided = poll(&q.ws.hitw[pose]);
                 if (uni(decided)) {  // another unit of this pose already found a collision
                     if (lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
                     continue;
@@ -498,11 +512,9 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
             }
             pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, coef, upidx, vtU, vtL, lane);
-            // distance: FP32 leaf-distance error bound (a generous multiple of the
-            // transform and closest-point rounding at this coordinate scale), and
-            // the absolute rounding allowance of the sphere bound
-            const float tnorm = sqrtf(P.t[0] * P.t[0] + P.t[1] * P.t[1] + P.t[2] * P.t[2]);
-            e_abs = 256.0f * 0x1p-24f * (tnorm + 3.5f * (MA.max_abs + MB.max_abs));
+            // distance: FP32 leaf-distance error bound, and the absolute
+            // rounding allowance of the sphere bound
+            e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
             e_sph = 64.0f * 0x1p-24f *
                     (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
         }
@@ -514,7 +526,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         uint32_t s_tpre[EMAX + 1] = {0, 64, 64, 64, 64};
         bool have_frame;
         uint32_t top = 0, lq_count = 0;
-        bool hit = false, overflow = false, pair_overflow = false;
+        bool hit = false, overflow = false, pair_overflow = false, fix_overflow = false;
         // shared: other units of this pose may exist, so the per-pose answer
         // in device memory is read and merged while traversing
         bool shared = from_item;
@@ -554,7 +566,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             }
             if (MODE == MODE_DIST) {
                 uint32_t g = 0;
-                if (lane == 0) g = rmw_read(&q.ws.best32[pose]);
+                if (lane == 0) g = poll(&q.ws.best32[pose]);
                 best32 = __uint_as_float(uni(g));
             }
             have_frame = false;
@@ -690,11 +702,11 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 next_sync = steps + kSyncPeriod;
                 if (MODE == MODE_BOOL) {
                     uint32_t d = 0;
-                    if (lane == 0) d = rmw_read(&q.ws.hitw[pose]);
+                    if (lane == 0) d = poll(&q.ws.hitw[pose]);
                     if (uni(d)) break;
                 } else if (MODE == MODE_DIST) {
                     uint32_t g = 0;
-                    if (lane == 0) g = rmw_read(&q.ws.best32[pose]);
+                    if (lane == 0) g = poll(&q.ws.best32[pose]);
                     best32 = fminf(best32, __uint_as_float(uni(g)));
                 }
             }
@@ -722,6 +734,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 const uint32_t lq_old = lq_count;
                 lq_count -= n_take;
                 int res = 0;
+                float dres = INFINITY;
                 bool active = lane < total;
                 uint32_t triA = 0, triB = 0;
                 V3<float> a[3], b[3];
@@ -743,21 +756,15 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     load_tri(MB.tris, triB, b);
 #pragma unroll
                     for (int v = 0; v < 3; v++) a[v] = xform_f32(P, a0[v]);
-                    if (MODE != MODE_DIST) {
-                        res = tri_tri_f32(a, b);
-                        if (res == 2) {
-                            V3<double> a64[3], b64[3];
-#pragma unroll
-                            for (int v = 0; v < 3; v++) {
-                                a64[v] = xform_f64(P, a0[v]);
-                                b64[v] = to64(b[v]);
-                            }
-                            res = tri_tri_f64(a64, b64) ? 3 : 4;  // 3/4: FP64-decided hit/miss
-                        }
-                    } else {
-                        int s32 = tri_tri_f32(a, b);
+                    // 0 disjoint, 1 intersecting, 2 undecided in FP32 (decided by the FP64 stage)
+                    res = tri_tri_f32(a, b);
+                    if (MODE == MODE_DIST) {
+                        // undecided pairs also get their FP32 feature distance:
+                        // it is accurate if they are disjoint and too large
+                        // (never too small) if they intersect, so the running
+                        // bound stays safe; the FP64 stage decides them
                         float d32 = 0.0f;
-                        if (s32 == 0) {
+                        if (res != 1) {
                             V3<float> ar[3], br[3];
 #pragma unroll
                             for (int v = 0; v < 3; v++) {
@@ -766,14 +773,17 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                             }
                             d32 = sqrtf(tri_tri_dist2(ar, br));
                         }
-                        res = __float_as_int(d32);
+                        dres = d32;
                     }
                 }
                 cnt.tri_tests += total;
                 cnt.tri_bytes += 72ull * total;
+                // leaf pairs for the FP64 stage: undecided intersections, and
+                // distances that could be the minimum
+                bool defer;
                 if (MODE == MODE_BOOL || MODE == MODE_PAIRS) {
-                    bool h = active && (res == 1 || res == 3);
-                    cnt.tri_fp64 += __popcll(__ballot(active && res >= 3));
+                    bool h = active && res == 1;
+                    defer = active && res == 2;
                     uint64_t mh = __ballot(h);
                     if (mh) {
                         hit = true;
@@ -795,40 +805,35 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                         if (b0 + nh > q.pair_cap) pair_overflow = true;
                     }
                 } else {
-                    float d32 = active ? __int_as_float(res) : INFINITY;
-                    float wmin = wave_min(d32);
+                    // a certified intersection is distance 0: the pose is done
+                    if (__ballot(active && res == 1)) {
+                        best64 = 0.0;
+                        dres = 0.0f;
+                    }
+                    float wmin = wave_min(dres);
                     if (wmin < best32) {
                         best32 = wmin;
                         if (shared && lane == 0)
                             __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best32), __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    const float tau2 = add_up(best32, 2.0f * e_abs);
-                    bool refine = active && d32 <= tau2;
-                    cnt.tri_fp64 += __popcll(__ballot(refine));
-                    double d64 = INFINITY;
-                    if (refine) {
-                        V3<float> a0[3];
-                        load_tri(MA.tris, triA, a0);
-                        V3<double> a64[3], b64[3];
-#pragma unroll
-                        for (int v = 0; v < 3; v++) {
-                            a64[v] = xform_f64(P, a0[v]);
-                            b64[v] = to64(b[v]);
-                        }
-                        if (tri_tri_f64(a64, b64)) {
-                            d64 = 0.0;
-                        } else {
-                            V3<double> ar[3], br[3];
-#pragma unroll
-                            for (int v = 0; v < 3; v++) {
-                                ar[v] = vsub(a64[v], a64[0]);
-                                br[v] = vsub(b64[v], a64[0]);
-                            }
-                            d64 = sqrt(tri_tri_dist2(ar, br));
-                        }
+                    defer = active && (res == 2 || (res == 0 && dres <= add_up(best32, 2.0f * e_abs)));
+                }
+                const uint64_t md = __ballot(defer);
+                if (md) {
+                    const uint32_t nd = __popcll(md);
+                    uint32_t f0 = 0;
+                    if (lane == 0) f0 = atomicAdd(&hdr->fix_count, nd);
+                    f0 = uni(f0);
+                    if (defer) {
+                        const uint32_t idx = f0 + mbcnt(md);
+                        // an undecided pair is stored with distance 0, which the
+                        // FP64 stage's final-bound filter always keeps
+                        const uint32_t dw = res == 2 ? 0u : __float_as_uint(dres);
+                        if (idx < q.ws.fix_cap) q.ws.fix[idx] = make_uint4(pose, triA, triB, dw);
                     }
-                    best64 = fmin(best64, wave_min(d64));
+                    if (f0 + nd > q.ws.fix_cap) fix_overflow = true;
+                    cnt.tri_fp64 += nd;
                 }
                 wave_sync();
                 continue;
@@ -840,7 +845,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 next_look = steps + kDonatePeriod;
                 uint32_t want = 0;
                 if (lane == 0) {
-                    unsigned long long ht = rmw_read64((unsigned long long *)&hdr->q_head);
+                    unsigned long long ht = poll64((unsigned long long *)&hdr->q_head);
                     uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
                     want = h > t ? min(h - t, min(top / 2, kMaxDonate)) : 0u;
                 }
@@ -1036,6 +1041,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         // ---- results of this unit ----
         if (lane == 0) {
             if (overflow) q.status[pose] = 1;            // CBVH_POSE_STACK_OVERFLOW
+            else if (fix_overflow) q.status[pose] = 3;   // CBVH_POSE_FP64_OVERFLOW
             else if (pair_overflow) q.status[pose] = 2;  // CBVH_POSE_PAIR_OVERFLOW
             if (MODE == MODE_DIST) {
                 if (best32 < INFINITY)
@@ -1092,6 +1098,64 @@ __global__ void init_kernel(WsHeader *hdr, uint8_t *hit, uint8_t *status, unsign
         if (pair_cnt) {
             pair_cnt[i] = 0;
             pair_cursor[i] = 0;
+        }
+    }
+}
+
+// FP64 stage, one thread per deferred leaf pair: decides the intersections
+// that FP32 left undecided, and refines every distance within the final
+// FP32 bound's reach (2 e of the pose's best FP32 distance) exactly.
+template <int MODE>
+__global__ __launch_bounds__(256) void fix_kernel(QueryArgs q)
+{
+    const uint32_t total = min(q.ws.hdr->fix_count, q.ws.fix_cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint4 f = q.ws.fix[i];
+        const uint32_t pose = f.x;
+        if (MODE == MODE_BOOL && q.hit[pose]) continue;
+        const float *pp = q.poses + 12 * (size_t)pose;
+        if (MODE == MODE_DIST) {
+            const float e = dist_err_abs(pp, q.A.max_abs, q.B.max_abs);
+            if (__uint_as_float(f.w) > add_up(__uint_as_float(q.ws.best32[pose]), 2.0f * e)) continue;
+        }
+        Pose P;
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) P.R[3 * r + c] = pp[4 * r + c];
+            P.t[r] = pp[4 * r + 3];
+        }
+        V3<float> a0[3], b0[3];
+        load_tri(q.A.tris, f.y, a0);
+        load_tri(q.B.tris, f.z, b0);
+        V3<double> a64[3], b64[3];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            a64[v] = xform_f64(P, a0[v]);
+            b64[v] = to64(b0[v]);
+        }
+        const bool inter = tri_tri_f64(a64, b64);
+        if (MODE == MODE_BOOL) {
+            if (inter) q.hit[pose] = 1;
+        } else if (MODE == MODE_PAIRS) {
+            if (inter) {
+                q.hit[pose] = 1;
+                const uint32_t idx = atomicAdd(&q.ws.hdr->pair_count, 1u);
+                if (idx < q.pair_cap) q.ws.pair_raw[idx] = make_uint4(pose, q.A.perm[f.y], q.B.perm[f.z], 0u);
+                else if (q.status[pose] == 0) q.status[pose] = 2;  // CBVH_POSE_PAIR_OVERFLOW
+            }
+        } else {
+            double d = 0.0;
+            if (!inter) {
+                V3<double> ar[3], br[3];
+#pragma unroll
+                for (int v = 0; v < 3; v++) {
+                    ar[v] = vsub(a64[v], a64[0]);
+                    br[v] = vsub(b64[v], a64[0]);
+                }
+                d = sqrt(tri_tri_dist2(ar, br));
+            }
+            atomicMin(&q.ws.best64[pose], (unsigned long long)__double_as_longlong(d));
         }
     }
 }
@@ -1249,10 +1313,6 @@ uint32_t env_u32(const char *name, uint32_t dflt)
     return x ? (uint32_t)x : dflt;
 }
 
-// waves per CU when the LDS state allows it (measured best for the
-// collision workloads: fewer leave latency uncovered, more thrash L2)
-constexpr uint32_t kWavesPerCu = 9;
-
 template <int K, int BITS, int MODE>
 hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
@@ -1261,8 +1321,15 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus < 1) cus = 256;
-    uint32_t per_cu = (uint32_t)(160u * 1024u / (L.total + 256u));
-    per_cu = min(per_cu, env_u32("CBVH_WAVES_PER_CU", kWavesPerCu));
+    // as many waves as fit on a CU at once (registers and LDS): the waves
+    // are persistent, so every one of them must be resident
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE>),
+                                                     WAVE, L.total) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();  // clear a failed query's error; fall back to the LDS bound
+        occ = (int)(160u * 1024u / (L.total + 256u));
+    }
+    uint32_t per_cu = min((uint32_t)occ, env_u32("CBVH_WAVES_PER_CU", 32u));
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
     uint32_t grid = (uint32_t)cus * per_cu;
@@ -1328,6 +1395,16 @@ hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t 
     }
     hipError_t e = launch_any(q, lim, s);
     if (e != hipSuccess) return e;
+    {
+        // the FP64 stage: its pair count is known on the device only, so a
+        // fixed grid strides over it
+        dim3 grid(1024), block(256);
+        if (q.mode == MODE_BOOL) hipLaunchKernelGGL(fix_kernel<MODE_BOOL>, grid, block, 0, s, q);
+        else if (q.mode == MODE_PAIRS) hipLaunchKernelGGL(fix_kernel<MODE_PAIRS>, grid, block, 0, s, q);
+        else hipLaunchKernelGGL(fix_kernel<MODE_DIST>, grid, block, 0, s, q);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (dist) {
         hipLaunchKernelGGL(dist_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, q.ws.best64, q.dist, n);
     } else if (pairs) {
