@@ -181,7 +181,8 @@ typedef struct {
     uint64_t t_end;          /* ... when the last wave exited */
     uint64_t max_pose_steps; /* most traversal steps (node + leaf) one work unit needed */
     uint64_t wait_timeouts;  /* 1 if a wavefront gave up waiting for work (never expected; results invalid) */
-    uint64_t reserved[2];
+    uint64_t node_steps;     /* node steps: one frame of children decoded and tested (up to 64 records) */
+    uint64_t leaf_steps;     /* leaf steps: up to 64 triangle pairs tested */
 } cbvh_stats_t;
 
 cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream);

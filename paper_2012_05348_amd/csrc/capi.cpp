@@ -346,6 +346,8 @@ cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats
     out->t_end = h.counters[cbvh::C_T_END];
     out->max_pose_steps = h.counters[cbvh::C_MAX_POSE_STEPS];
     out->wait_timeouts = h.error;
+    out->node_steps = h.counters[cbvh::C_NODE_STEPS];
+    out->leaf_steps = h.counters[cbvh::C_LEAF_STEPS];
     return CBVH_OK;
 }
 

@@ -38,6 +38,8 @@ enum Counter : int {
     C_T_DRAIN,         // min wall clock at which a wave found the pose queue empty
     C_T_END,           // max wall clock of a wave's exit
     C_MAX_POSE_STEPS,  // most node + leaf steps one work unit used
+    C_NODE_STEPS,      // node steps (each decodes one frame of children)
+    C_LEAF_STEPS,      // leaf steps (each tests up to 64 triangle pairs)
     C_NUM = 16
 };
 
@@ -49,7 +51,8 @@ struct WsHeader {
     uint32_t pair_count;  // pairs appended (may exceed capacity)
     uint32_t error;       // a wave gave up waiting for an item (never expected)
     uint32_t fix_count;   // leaf pairs handed to the FP64 stage (may exceed capacity)
-    uint32_t pad0[28];
+    uint32_t helpers;     // waves that found the pose queue empty
+    uint32_t pad0[27];
     uint32_t q_head;      // next item slot to claim (8-byte aligned: read together with q_tail)
     uint32_t q_tail;      // next item slot to reserve
     uint32_t pad1[30];
@@ -92,6 +95,9 @@ struct QueryArgs {
     uint8_t *status;
     uint32_t pair_cap;
     uint32_t no_split;  // never donate work; exhausting the LDS stack then fails the pose
+    uint32_t max_pop;   // entries one node step may pop (1..8)
+    uint32_t donate_min_steps;  // a unit feeds waiting waves only after this many steps
+    uint32_t max_helpers;       // waves that stay to take items once the poses are gone
     Workspace ws;
 };
 

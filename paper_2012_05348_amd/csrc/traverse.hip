@@ -31,8 +31,10 @@ namespace cbvh {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int EMAX = 4;                              // node-pair expansions per node step
-constexpr int TA_MAX = EMAX * (int)kMaxBranching;    // A records transformed per step
+constexpr int PMAX = 8;                              // entries popped by one node step (most)
+constexpr uint32_t TMAX = 64;                        // child-pair tests of one node step (most): one pass
+constexpr uint32_t AMAX = 32;                        // A records of one node step (most)
+constexpr int TA_MAX = (int)AMAX;                    // A records transformed per step
 constexpr int MAX_FRAMES = 64;
 constexpr uint32_t REC_BITS = 13;                    // entry: recA | recB << 13 | frame << 26
 constexpr uint32_t REC_MASK = (1u << REC_BITS) - 1u;
@@ -76,7 +78,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 // per-wave state layout (identical on host and device)
 // ---------------------------------------------------------------------------
 struct Layout {
-    uint32_t coef, upidx, vtU, vtL, misc, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
+    uint32_t coef, upidx, vtU, vtL, meta, mpar, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
 };
 
 __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
@@ -92,7 +94,8 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.upidx = take(4 * K);
     L.vtU = take(4 * K);
     L.vtL = take(4 * K);
-    L.misc = take(16);
+    L.meta = take(4 * PMAX);
+    L.mpar = take(16 * PMAX);
     L.frame_end = take(4 * MAX_FRAMES);
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
@@ -284,9 +287,16 @@ __device__ __forceinline__ float dist_err_abs(const float *pose, float maxA, flo
 // 16-bit reciprocal for n in [1, 8]: (x * r) >> 16 == x / n for x < 64
 __device__ __forceinline__ uint32_t recip16(uint32_t n) { return (65536u + n - 1u) / n; }
 
+// An entry popped by a node step, as its tests see it: first A record and
+// first B record (relative to the frame), B's child count, first test.
+__device__ __forceinline__ uint32_t meta_word(uint32_t aoff, uint32_t boff, uint32_t nb, uint32_t tpre)
+{
+    return aoff | (boff << 8) | (nb << 16) | (tpre << 24);
+}
+
 struct Counters {
     unsigned long long bv_tests = 0, tri_tests = 0, tri_fp64 = 0, expansions = 0, node_bytes = 0, tri_bytes = 0,
-                       donated = 0;
+                       donated = 0, node_steps = 0, leaf_steps = 0;
     uint32_t max_entries = 0, max_records = 0, max_steps = 0;
 };
 
@@ -346,8 +356,10 @@ constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 // is when waiting waves exit.  Per-pose answers (hit flag, best distances)
 // are merged in device memory, so results do not depend on the split.
 // ---------------------------------------------------------------------------
+// Collision modes fit 3 waves per SIMD (168 VGPRs); distance mode needs more.
 template <int K, int BITS, int MODE>
-__global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits lim)
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(MODE == MODE_DIST ? 2 : 3)))
+void traverse_kernel(QueryArgs q, StackLimits lim)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t lane = __lane_id();
@@ -367,8 +379,11 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
     uint2 *lq = (uint2 *)(base + LY.lq);
     float *lq_lb = (float *)(base + LY.lq_lb);
     uint32_t *scratch = (uint32_t *)(base + LY.scratch);
+    uint32_t *meta = (uint32_t *)(base + LY.meta);
+    uint4 *mpar = (uint4 *)(base + LY.mpar);
 
-    constexpr uint32_t IW = words_of_item(K);       // dwords per item
+    constexpr uint32_t IW = words_of_item(K);
+    constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass       // dwords per item
     constexpr uint32_t IPI = (uint32_t)WAVE / IW;   // items written per wave instruction
     const DevModel &MA = q.A;
     const DevModel &MB = q.B;
@@ -433,10 +448,12 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         return ok ? n : 0u;
     };
 
-    bool poses_left = true;
+    bool poses_left = true, helper = false;
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
     float e_abs = 0.0f, e_sph = 0.0f;
+    // this lane's slab (lane mod K) of the pose's support-function transform
+    const uint32_t my_k = lane % (uint32_t)K;
     const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
 
     for (;;) {
@@ -457,6 +474,13 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         }
         if (!poses_left) {
             if (!can_donate) break;
+            if (!helper) {
+                // the first time: stay as a helper only while few enough do
+                uint32_t hn = 0;
+                if (lane == 0) hn = rmw_add(&hdr->helpers, 1u);
+                if (uni(hn) >= q.max_helpers) break;
+                helper = true;
+            }
             uint32_t slot = 0;
             if (lane == 0) slot = rmw_add(&hdr->q_head, 1u);
             slot = uni(slot);
@@ -520,10 +544,9 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         }
 
         // ---- initial state ----
-        uint32_t f_id = 0, f_base = 0, f_nA = 1, f_total_tasks = 1;
-        uint32_t s_aoff[EMAX] = {0, 0, 0, 0};
-        uint32_t s_boff[EMAX] = {1, 0, 0, 0}, s_nb[EMAX] = {1, 0, 0, 0};
-        uint32_t s_tpre[EMAX + 1] = {0, 64, 64, 64, 64};
+        // current frame: the records decoded by the last node step, waiting
+        // for their child-pair tests (f_ns entries described in `meta`)
+        uint32_t f_id = 0, f_base = 0, f_nA = 1, f_ns = 1, f_tasks = 1;
         bool have_frame;
         uint32_t top = 0, lq_count = 0;
         bool hit = false, overflow = false, pair_overflow = false, fix_overflow = false;
@@ -544,6 +567,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
 #pragma unroll
                 for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
             }
+            if (lane == 0) meta[0] = meta_word(0, 1, 1, 0);
             have_frame = true;
         } else {
             // the item's pair already passed its BV test: records 0 and 1 hold it
@@ -580,20 +604,21 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             if (have_frame) {
                 have_frame = false;
                 // -------- transform A's records of the frame into B's frame --------
-                for (uint32_t t = lane; t < f_nA * K; t += WAVE) {
-                    uint32_t i = t / K, k = t - i * K;
-                    const float *b = rbnd + (size_t)(f_base + i) * 2 * K;
-                    uint32_t up = upidx[k];
-                    float U = vtU[k], L = vtL[k];
-#pragma unroll
-                    for (int m = 0; m < 3; m++) {
-                        uint32_t ix = (up >> (8 * m)) & 0xFFu;
-                        float c = coef[3 * k + m];
-                        U = __builtin_fmaf(c, b[ix], U);
-                        L = __builtin_fmaf(c, b[ix ^ 1u], L);
+                // lane = (record c, slab my_k): CPL records per pass
+                const float my_c0 = coef[3 * my_k], my_c1 = coef[3 * my_k + 1], my_c2 = coef[3 * my_k + 2];
+                const uint32_t my_up = upidx[my_k];
+                const float my_vU = vtU[my_k], my_vL = vtL[my_k];
+                for (uint32_t c0 = 0; c0 < f_nA; c0 += CPL) {
+                    const uint32_t c = c0 + lane / (uint32_t)K;
+                    if (lane < CPL * (uint32_t)K && c < f_nA) {
+                        const float *b = rbnd + (size_t)(f_base + c) * 2 * K;
+                        const uint32_t i0 = my_up & 0xFFu, i1 = (my_up >> 8) & 0xFFu, i2 = (my_up >> 16) & 0xFFu;
+                        const float U = __builtin_fmaf(my_c2, b[i2], __builtin_fmaf(my_c1, b[i1], __builtin_fmaf(my_c0, b[i0], my_vU)));
+                        const float L =
+                            __builtin_fmaf(my_c2, b[i2 ^ 1u], __builtin_fmaf(my_c1, b[i1 ^ 1u], __builtin_fmaf(my_c0, b[i0 ^ 1u], my_vL)));
+                        ta[2 * K * c + 2 * my_k] = L;
+                        ta[2 * K * c + 2 * my_k + 1] = U;
                     }
-                    ta[2 * K * i + 2 * k] = L;
-                    ta[2 * K * i + 2 * k + 1] = U;
                 }
                 if (MODE == MODE_DIST && lane < f_nA) {
                     // circumscribed sphere of the record's box, centre moved by the pose
@@ -605,92 +630,104 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     tsph[lane] = make_float4(cw.x, cw.y, cw.z, r);
                 }
                 wave_sync();
-                // -------- one child pair per lane --------
+                // -------- child-pair tests, 64 per pass --------
+                uint32_t mw[PMAX];
+#pragma unroll
+                for (int s = 0; s < PMAX; s++) mw[s] = meta[s];
                 const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
-                bool survive = false;
-                float lb = 0.0f;
-                uint32_t recA = 0, recB = 0;
-                if (lane < f_total_tasks) {
-                    uint32_t s = (lane >= s_tpre[1]) + (lane >= s_tpre[2]) + (lane >= s_tpre[3]);
-                    uint32_t nb = s == 0 ? s_nb[0] : s == 1 ? s_nb[1] : s == 2 ? s_nb[2] : s_nb[3];
-                    uint32_t ao = s == 0 ? s_aoff[0] : s == 1 ? s_aoff[1] : s == 2 ? s_aoff[2] : s_aoff[3];
-                    uint32_t bo = s == 0 ? s_boff[0] : s == 1 ? s_boff[1] : s == 2 ? s_boff[2] : s_boff[3];
-                    uint32_t tp = s == 0 ? s_tpre[0] : s == 1 ? s_tpre[1] : s == 2 ? s_tpre[2] : s_tpre[3];
-                    uint32_t local = lane - tp;
-                    uint32_t i = (local * recip16(nb)) >> 16, j = local - i * nb;
-                    uint32_t ia = ao + i;
-                    recA = f_base + ia;
-                    recB = f_base + bo + j;
-                    const float *tA = ta + 2 * K * ia;
-                    const float *bB = rbnd + (size_t)recB * 2 * K;
-                    if (MODE == MODE_DIST) {
-                        float g = 0.0f;
+                const uint32_t top0 = top;
+                float near_lb = INFINITY;
+                uint32_t near_slot = 0;
+                for (uint32_t t0 = 0; t0 < f_tasks; t0 += WAVE) {
+                    const uint32_t t = t0 + lane;
+                    bool survive = false;
+                    float lb = 0.0f;
+                    uint32_t recA = 0, recB = 0;
+                    if (t < f_tasks) {
+                        // the task's entry: the last one whose first task is <= t
+                        uint32_t w = mw[0];
 #pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
-                            gk *= (k < 3 ? 1.0f : w_diag);
-                            g = fmaxf(g, gk);
+                        for (int s = 1; s < PMAX; s++)
+                            if ((uint32_t)s < f_ns && (mw[s] >> 24) <= t) w = mw[s];
+                        const uint32_t aoff = w & 0xFFu, boff = (w >> 8) & 0xFFu, nb = (w >> 16) & 0xFFu;
+                        const uint32_t local = t - (w >> 24);
+                        const uint32_t i = (local * recip16(nb)) >> 16, j = local - i * nb;
+                        const uint32_t ia = aoff + i;
+                        recA = f_base + ia;
+                        recB = f_base + boff + j;
+                        const float *tA = ta + 2 * K * ia;
+                        const float *bB = rbnd + (size_t)recB * 2 * K;
+                        if (MODE == MODE_DIST) {
+                            float g = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < K; k++) {
+                                float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
+                                gk *= (k < 3 ? 1.0f : w_diag);
+                                g = fmaxf(g, gk);
+                            }
+                            // second lower bound: distance of the circumscribed spheres
+                            float4 sa = tsph[ia];
+                            float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
+                            float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
+                            float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                            float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
+                            float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
+                            lb = fmaxf(g * (1.0f - 0x1p-20f), gs);
+                            survive = lb <= tau;
+                        } else {
+                            bool sep = false;
+#pragma unroll
+                            for (int k = 0; k < K; k++) sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
+                            survive = !sep;
                         }
-                        // second lower bound: distance of the circumscribed spheres
-                        float4 sa = tsph[ia];
-                        float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
-                        float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
-                        float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
-                        float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
-                        float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
-                        lb = fmaxf(g * (1.0f - 0x1p-20f), gs);
-                        survive = lb <= tau;
-                    } else {
-                        bool sep = false;
-#pragma unroll
-                        for (int k = 0; k < K; k++) sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
-                        survive = !sep;
                     }
+                    // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
+                    uint32_t tA_w = 0, tB_w = 0;
+                    bool ll = false;
+                    if (survive) {
+                        tA_w = rtopo[recA];
+                        tB_w = rtopo[recB];
+                        ll = topo_leaf(tA_w) && topo_leaf(tB_w);
+                    }
+                    const uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
+                    const uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
+                    if (survive && ll) {
+                        const uint32_t slot = lq_count + mbcnt(m_ll);
+                        lq[slot] = make_uint2(tA_w, tB_w);
+                        if (MODE == MODE_DIST) lq_lb[slot] = lb;
+                    }
+                    if (survive && !ll) {
+                        const uint32_t slot = top + mbcnt(m_nd);
+                        ent[slot] = recA | (recB << REC_BITS) | (f_id << (2 * REC_BITS));
+                        if (MODE == MODE_DIST) ent_lb[slot] = lb;
+                    }
+                    if (MODE == MODE_DIST && n_nd > 0) {
+                        // remember the closest new node pair
+                        const float mlb = wave_min((survive && !ll) ? lb : INFINITY);
+                        if (mlb < near_lb) {
+                            const uint64_t win = __ballot(survive && !ll && lb == mlb);
+                            const uint32_t wl = (uint32_t)__ffsll((unsigned long long)win) - 1u;
+                            near_lb = mlb;
+                            near_slot = top + (uint32_t)__popcll(m_nd & ((1ull << wl) - 1ull));
+                        }
+                    }
+                    lq_count += n_ll;
+                    top += n_nd;
                 }
-                cnt.bv_tests += f_total_tasks;
-                // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
-                uint32_t tA_w = 0, tB_w = 0;
-                bool ll = false;
-                if (survive) {
-                    tA_w = rtopo[recA];
-                    tB_w = rtopo[recB];
-                    ll = topo_leaf(tA_w) && topo_leaf(tB_w);
-                }
-                uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
-                uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
-                if (lq_count + n_ll > lim.leafq || top + n_nd > lim.entries) {
-                    overflow = true;  // cannot happen: node steps check the room first
-                    break;
-                }
-                if (survive && ll) {
-                    uint32_t slot = lq_count + mbcnt(m_ll);
-                    lq[slot] = make_uint2(tA_w, tB_w);
-                    if (MODE == MODE_DIST) lq_lb[slot] = lb;
-                }
-                if (survive && !ll) {
-                    uint32_t slot = top + mbcnt(m_nd);
-                    ent[slot] = recA | (recB << REC_BITS) | (f_id << (2 * REC_BITS));
-                    if (MODE == MODE_DIST) ent_lb[slot] = lb;
-                }
-                lq_count += n_ll;
-                if (MODE == MODE_DIST && n_nd > 1) {
+                if (MODE == MODE_DIST && top - top0 > 1 && near_slot != top - 1) {
                     // put the closest new pair on top of the stack
-                    float mlb = wave_min((survive && !ll) ? lb : INFINITY);
-                    uint64_t win = __ballot(survive && !ll && lb == mlb);
-                    uint32_t wl = win ? (uint32_t)__ffsll((unsigned long long)win) - 1u : 0u;
-                    uint32_t wslot = top + (uint32_t)__popcll(m_nd & ((1ull << wl) - 1ull));
-                    uint32_t last = top + n_nd - 1;
                     wave_sync();
-                    if (lane == 0 && win && wslot != last) {
-                        uint32_t e0 = ent[wslot];
-                        float l0 = ent_lb[wslot];
-                        ent[wslot] = ent[last];
-                        ent_lb[wslot] = ent_lb[last];
+                    if (lane == 0) {
+                        const uint32_t last = top - 1;
+                        const uint32_t e0 = ent[near_slot];
+                        const float l0 = ent_lb[near_slot];
+                        ent[near_slot] = ent[last];
+                        ent_lb[near_slot] = ent_lb[last];
                         ent[last] = e0;
                         ent_lb[last] = l0;
                     }
                 }
-                top += n_nd;
+                cnt.bv_tests += f_tasks;
                 cnt.max_entries = max(cnt.max_entries, top);
                 wave_sync();
             }
@@ -777,6 +814,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     }
                 }
                 cnt.tri_tests += total;
+                cnt.leaf_steps++;
                 cnt.tri_bytes += 72ull * total;
                 // leaf pairs for the FP64 stage: undecided intersections, and
                 // distances that could be the minimum
@@ -841,7 +879,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
             if (top == 0) break;
 
             // -------- feed waiting waves with the bottom of the stack --------
-            if (can_donate && top >= 2 && steps >= next_look) {
+            if (can_donate && top >= 2 && steps >= next_look && steps >= q.donate_min_steps) {
                 next_look = steps + kDonatePeriod;
                 uint32_t want = 0;
                 if (lane == 0) {
@@ -874,85 +912,50 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 }
             }
 
-            // -------- node step: choose a batch of entries whose tests fit one wave --------
+            // -------- node step: pop the top entries whose children fit one decode pass --------
             const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
-            uint32_t my_e = 0, my_na = 0, my_nb = 0, my_tasks = 0, my_pA = 0, my_pB = 0;
-            if (lane < (uint32_t)EMAX && lane < top) {
+            // lane l <= PMAX reads the (l+1)-th entry from the top
+            uint32_t my_e = 0, my_pA = 0, my_pB = 0, my_fend = 0, my_na = 0, my_nb = 0;
+            if (lane <= (uint32_t)PMAX && lane < top) {
                 my_e = ent[top - 1 - lane];
-                uint32_t rA = my_e & REC_MASK, rB = (my_e >> REC_BITS) & REC_MASK;
+                const uint32_t rA = my_e & REC_MASK, rB = (my_e >> REC_BITS) & REC_MASK;
                 my_pA = rtopo[rA];
                 my_pB = rtopo[rB];
+                my_fend = frame_end[my_e >> (2 * REC_BITS)];
                 my_na = topo_leaf(my_pA) ? 1u : topo_count(my_pA);
                 my_nb = topo_leaf(my_pB) ? 1u : topo_count(my_pB);
-                my_tasks = my_na * my_nb;
-                if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_tasks = my_na = my_nb = 0;
+                if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_na = my_nb = 0;  // culled
             }
-            uint32_t n_pop = 0, acc = 0;
-            uint32_t e_s[EMAX], na_s[EMAX], nb_s[EMAX], pA_s[EMAX], pB_s[EMAX];
+            // inclusive prefix over lanes 0..PMAX-1 of (A records, B records, tests), packed in one word
+            const uint32_t my_tk = my_na * my_nb;
+            const uint32_t my_pk = lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16)) : 0u;
+            uint32_t pk = my_pk;
 #pragma unroll
-            for (int s = 0; s < EMAX; s++) {
-                e_s[s] = lane_of(my_e, s);
-                na_s[s] = lane_of(my_na, s);
-                nb_s[s] = lane_of(my_nb, s);
-                pA_s[s] = lane_of(my_pA, s);
-                pB_s[s] = lane_of(my_pB, s);
-                uint32_t tk = lane_of(my_tasks, s);
-                // proximity queries dive one expansion at a time until a first
-                // leaf distance exists: without a bound nothing is culled
-                bool dive = MODE == MODE_DIST && best32 == INFINITY && s > 0;
-                bool ok = !dive && (uint32_t)s < top && n_pop == (uint32_t)s && acc + tk <= (uint32_t)WAVE;
-                if (ok) {
-                    n_pop++;
-                    acc += tk;
-                }
+            for (int o = 1; o < PMAX; o <<= 1) {
+                const uint32_t x = __shfl_up(pk, o);
+                if (lane >= (uint32_t)o) pk += x;
             }
-            // the new frame sits on top of the frame of the next remaining entry
-            uint32_t remaining = top - n_pop;
-            uint32_t new_id = 0, new_base = 0;
-            if (remaining > 0) {
-                uint32_t f_below = uni(ent[remaining - 1]) >> (2 * REC_BITS);
-                new_id = f_below + 1;
-                new_base = uni(frame_end[f_below]);
-            }
-            // slots of the new frame: A lists first, then B lists
-            uint32_t nA_tot = 0, nB_tot = 0, ns = 0, tasks_tot = 0;
-            uint32_t n_aoff[EMAX] = {0, 0, 0, 0}, n_na[EMAX] = {0, 0, 0, 0}, n_nb[EMAX] = {0, 0, 0, 0};
-            uint32_t n_src[EMAX] = {0, 0, 0, 0}, n_tpre[EMAX + 1] = {64, 64, 64, 64, 64};
-#pragma unroll
-            for (int s = 0; s < EMAX; s++) {
-                if ((uint32_t)s < n_pop && na_s[s] > 0) {
-#pragma unroll
-                    for (int d = 0; d < EMAX; d++)
-                        if ((uint32_t)d == ns) {
-                            n_aoff[d] = nA_tot;
-                            n_na[d] = na_s[s];
-                            n_nb[d] = nb_s[s];
-                            n_src[d] = (uint32_t)s;
-                            n_tpre[d] = tasks_tot;
-                        }
-                    nA_tot += na_s[s];
-                    nB_tot += nb_s[s];
-                    tasks_tot += na_s[s] * nb_s[s];
-                    ns++;
-                }
-            }
-            uint32_t n_boff[EMAX] = {0, 0, 0, 0};
-            {
-                uint32_t accb = nA_tot;
-#pragma unroll
-                for (int d = 0; d < EMAX; d++) {
-                    n_boff[d] = accb;
-                    accb += n_nb[d];
-                }
-            }
-            const uint32_t total_rec = nA_tot + nB_tot;
-            // room for the new frame and for every possible survivor?
-            const bool fits = new_id < (uint32_t)MAX_FRAMES && new_base + total_rec <= lim.records &&
-                              new_base + total_rec <= REC_MASK + 1u && remaining + tasks_tot <= lim.entries;
-            if (!fits) {
-                // hand every pending pair (node pairs with their decoded
-                // bounds, and queued leaf pairs) to the item queue; the
-                // unit ends here
+            const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = pk >> 16;
+            // with lane+1 entries popped the new frame sits on top of the frame of
+            // the next remaining entry, which lane+1 has read
+            const uint32_t nx_e = __shfl_down(my_e, 1), nx_fend = __shfl_down(my_fend, 1);
+            const uint32_t rem_l = top - 1u - lane;
+            const uint32_t nbase_l = rem_l > 0 ? nx_fend : 0u;
+            const uint32_t nid_l = rem_l > 0 ? (nx_e >> (2 * REC_BITS)) + 1u : 0u;
+            // proximity queries dive one expansion at a time until a first leaf
+            // distance exists: without a bound nothing is culled
+            const bool dive = MODE == MODE_DIST && best32 == INFINITY;
+            // (a frame stays live while any of its entries is pending, so wider
+            // frames pin more records: one test pass per step keeps frames small)
+            const bool ok = lane < q.max_pop && lane < top && (!dive || lane == 0) && inA <= AMAX &&
+                            inA + inB <= (uint32_t)WAVE && inT <= TMAX && rem_l + inT <= lim.entries &&
+                            lq_count + inT <= lim.leafq && nid_l < (uint32_t)MAX_FRAMES &&
+                            nbase_l + inA + inB <= lim.records && nbase_l + inA + inB <= REC_MASK + 1u;
+            const uint32_t n_pop = (uint32_t)__builtin_ctzll(~__ballot(ok));  // leading lanes that fit
+            if (n_pop == 0) {
+                // not even the top entry fits the LDS state: hand every pending
+                // pair (node pairs with their decoded bounds, and queued leaf
+                // pairs) to the item queue; the unit ends here
                 const uint32_t n_items = top + lq_count;
                 if (can_donate && publish(pose, n_items, top, best32) == n_items) {
                     cnt.donated += n_items;
@@ -962,29 +965,55 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 }
                 break;
             }
-            top = remaining;
-            if (ns == 0) continue;  // every popped entry was culled
-            // decode: one lane per new record (register staging: the new
-            // frame may overwrite the popped entries' own frames)
+            const int last = (int)n_pop - 1;
+            const uint32_t nA_tot = lane_of(inA, last), total_rec = nA_tot + lane_of(inB, last);
+            const uint32_t tasks_tot = lane_of(inT, last);
+            const uint32_t new_base = lane_of(nbase_l, last), new_id = lane_of(nid_l, last);
+            top -= n_pop;
+            // popped entries with tests to run get a meta word each; culled ones drop out
+            const bool act = lane < n_pop && my_tk > 0;
+            const uint64_t m_act = __ballot(act);
+            const uint32_t ns = __popcll(m_act);
+            if (ns == 0) continue;
+            if (act) {
+                const uint32_t ex = pk - my_pk;  // exclusive prefix
+                const uint32_t slot = mbcnt(m_act);
+                meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, ex >> 16);
+                mpar[slot] = make_uint4(my_e & REC_MASK, (my_e >> REC_BITS) & REC_MASK, my_pA, my_pB);
+            }
+            {
+                uint32_t nbytes = 0;
+                if (act) nbytes = (topo_leaf(my_pA) ? 0u : topo_count(my_pA) * code_bytes_A) +
+                                  (topo_leaf(my_pB) ? 0u : topo_count(my_pB) * code_bytes_B);
+#pragma unroll
+                for (int o = 1; o < PMAX; o <<= 1) nbytes += __shfl_xor(nbytes, o);
+                cnt.node_bytes += lane_of(nbytes, 0);
+            }
+            wave_sync();
+            // decode: one lane per new record, A records first, then B records
+            // (register staging: the new frame may overwrite the popped
+            // entries' own records)
             uint32_t my_topo = 0;
             float my_b[2 * K];
-            bool dec = lane < total_rec;
+            const bool dec = lane < total_rec;
             if (dec) {
-                bool sideA = lane < nA_tot;
-                uint32_t r = sideA ? lane : lane - nA_tot;
-                uint32_t d = 0;
+                const bool sideA = lane < nA_tot;
+                uint32_t e = 0, off = sideA ? 0u : nA_tot;
 #pragma unroll
-                for (int x = 1; x < EMAX; x++) {
-                    uint32_t off = sideA ? n_aoff[x] : n_boff[x] - nA_tot;
-                    if ((uint32_t)x < ns && r >= off) d = (uint32_t)x;
+                for (int s = 1; s < PMAX; s++) {
+                    if ((uint32_t)s < ns) {
+                        const uint32_t w = meta[s];
+                        const uint32_t o = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
+                        if (lane >= o) {
+                            e = (uint32_t)s;
+                            off = o;
+                        }
+                    }
                 }
-                uint32_t off = sideA ? (d == 0 ? n_aoff[0] : d == 1 ? n_aoff[1] : d == 2 ? n_aoff[2] : n_aoff[3])
-                                     : (d == 0 ? n_boff[0] : d == 1 ? n_boff[1] : d == 2 ? n_boff[2] : n_boff[3]) - nA_tot;
-                uint32_t c = r - off;
-                uint32_t src = d == 0 ? n_src[0] : d == 1 ? n_src[1] : d == 2 ? n_src[2] : n_src[3];
-                uint32_t e = src == 0 ? e_s[0] : src == 1 ? e_s[1] : src == 2 ? e_s[2] : e_s[3];
-                uint32_t prec = sideA ? (e & REC_MASK) : ((e >> REC_BITS) & REC_MASK);
-                uint32_t ptopo = rtopo[prec];
+                const uint4 pr = mpar[e];
+                const uint32_t c = lane - off;
+                const uint32_t prec = sideA ? pr.x : pr.y;
+                const uint32_t ptopo = sideA ? pr.z : pr.w;
                 const float *pb = rbnd + (size_t)prec * 2 * K;
                 if (topo_leaf(ptopo)) {
                     my_topo = ptopo;
@@ -992,7 +1021,7 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                     for (int k = 0; k < 2 * K; k++) my_b[k] = pb[k];
                 } else {
                     const DevModel &M = sideA ? MA : MB;
-                    uint32_t node = topo_first(ptopo) + c;
+                    const uint32_t node = topo_first(ptopo) + c;
                     my_topo = M.topo[node];
                     decode_node<K, BITS>(M, node, my_topo, pb, my_b);
                 }
@@ -1004,36 +1033,16 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
                 for (int k = 0; k < 2 * K; k++) rbnd[(size_t)(new_base + lane) * 2 * K + k] = my_b[k];
             }
             if (lane == 0) frame_end[new_id] = new_base + total_rec;
-            {
-                unsigned long long nbytes = 0;
-#pragma unroll
-                for (int d = 0; d < EMAX; d++) {
-                    if ((uint32_t)d < ns) {
-                        uint32_t src = n_src[d];
-                        uint32_t pa = src == 0 ? pA_s[0] : src == 1 ? pA_s[1] : src == 2 ? pA_s[2] : pA_s[3];
-                        uint32_t pb2 = src == 0 ? pB_s[0] : src == 1 ? pB_s[1] : src == 2 ? pB_s[2] : pB_s[3];
-                        if (!topo_leaf(pa)) nbytes += (unsigned long long)topo_count(pa) * code_bytes_A;
-                        if (!topo_leaf(pb2)) nbytes += (unsigned long long)topo_count(pb2) * code_bytes_B;
-                    }
-                }
-                cnt.node_bytes += nbytes;
-                cnt.expansions += ns;
-            }
+            cnt.expansions += ns;
+            cnt.node_steps++;
             cnt.max_records = max(cnt.max_records, new_base + total_rec);
             wave_sync();
             // the new frame becomes the current one
             f_id = new_id;
             f_base = new_base;
             f_nA = nA_tot;
-            f_total_tasks = tasks_tot;
-#pragma unroll
-            for (int d = 0; d < EMAX; d++) {
-                s_aoff[d] = n_aoff[d];
-                s_boff[d] = n_boff[d];
-                s_nb[d] = n_nb[d];
-                s_tpre[d] = (uint32_t)d < ns ? n_tpre[d] : 64u;
-            }
-            s_tpre[EMAX] = 64;
+            f_ns = ns;
+            f_tasks = tasks_tot;
             have_frame = true;
         }
         cnt.max_steps = max(cnt.max_steps, steps);
@@ -1064,6 +1073,8 @@ __global__ __launch_bounds__(WAVE) void traverse_kernel(QueryArgs q, StackLimits
         atomicAdd(&hdr->counters[C_NODE_BYTES], cnt.node_bytes);
         atomicAdd(&hdr->counters[C_TRI_BYTES], cnt.tri_bytes);
         atomicAdd(&hdr->counters[C_DONATED], cnt.donated);
+        atomicAdd(&hdr->counters[C_NODE_STEPS], cnt.node_steps);
+        atomicAdd(&hdr->counters[C_LEAF_STEPS], cnt.leaf_steps);
         atomicMax(&hdr->counters[C_MAX_ENTRIES], (unsigned long long)cnt.max_entries);
         atomicMax(&hdr->counters[C_MAX_RECORDS], (unsigned long long)cnt.max_records);
         atomicMax(&hdr->counters[C_MAX_POSE_STEPS], (unsigned long long)cnt.max_steps);
@@ -1304,7 +1315,17 @@ __global__ void decode_all_kernel(DevModel M, float *out)
     }
 }
 
-// Launch shape knob (for the tuner; default when unset or 0): CBVH_WAVES_PER_CU.
+// Launch knobs (for the tuner; defaults when unset or 0): CBVH_WAVES_PER_CU,
+// CBVH_MAX_POP (entries per node step), CBVH_DONATE_MIN_STEPS,
+// CBVH_MAX_HELPERS.
+//
+// Once the pose queue is empty only a few waves stay to take donated work
+// (one per CU): every wave that stays competes for issue slots with the
+// long units on the critical path, and units feed them only after some
+// steps, so that units about to finish do not split needlessly.  Measured
+// on MI355X over the collision and proximity workloads.
+constexpr uint32_t kDonateMinSteps = 16;
+constexpr uint32_t kHelpersPerCu = 1;
 uint32_t env_u32(const char *name, uint32_t dflt)
 {
     const char *v = getenv(name);
@@ -1335,7 +1356,11 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     uint32_t grid = (uint32_t)cus * per_cu;
     // without donation a wave beyond the pose count has nothing to do
     if (q.no_split && grid > q.n_poses) grid = q.n_poses;
-    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, q, lim);
+    QueryArgs qq = q;
+    qq.max_pop = min(env_u32("CBVH_MAX_POP", (uint32_t)PMAX), (uint32_t)PMAX);
+    qq.donate_min_steps = env_u32("CBVH_DONATE_MIN_STEPS", kDonateMinSteps);
+    qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * kHelpersPerCu);
+    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, qq, lim);
     return hipGetLastError();
 }
 
