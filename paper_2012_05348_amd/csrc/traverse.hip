@@ -64,6 +64,22 @@ __device__ __forceinline__ double wave_min(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
 }
+// DPP row shifts (within each row of 16 lanes; 0 where there is no source lane)
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 | N, 0xF, 0xF, true);
+}
+template <int N>
+__device__ __forceinline__ uint32_t row_shl(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 | N, 0xF, 0xF, true);
+}
+// value of x in lane src (all lanes must be active)
+__device__ __forceinline__ uint32_t gather(uint32_t x, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 {
 #pragma unroll
@@ -78,7 +94,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 // per-wave state layout (identical on host and device)
 // ---------------------------------------------------------------------------
 struct Layout {
-    uint32_t coef, upidx, vtU, vtL, meta, mpar, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
+    uint32_t xf, meta, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
 };
 
 __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
@@ -90,12 +106,8 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
         o += (bytes + 15u) & ~15u;
         return r;
     };
-    L.coef = take(12 * K);
-    L.upidx = take(4 * K);
-    L.vtU = take(4 * K);
-    L.vtL = take(4 * K);
+    L.xf = take(32 * K);
     L.meta = take(4 * PMAX);
-    L.mpar = take(16 * PMAX);
     L.frame_end = take(4 * MAX_FRAMES);
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
@@ -147,7 +159,9 @@ __device__ inline void dop18_cone(const double u[3], double alpha[3], int axis[3
     }
 }
 
-// Per-pose setup (lanes 0..K-1, one slab axis v_k of B each).  A's node
+// Per-pose setup (lanes 0..K-1, one slab axis v_k of B each).  The result
+// for slab k is two float4: (c_0, c_1, c_2, packed generator indices) and
+// (vtU, vtL, 0, 0), read back with two 16-byte LDS loads.  A's node
 // polytope {x : lo_j <= n_j.x <= hi_j} moved by the pose projects onto v_k
 // inside [L_k, U_k] with
 //   U_k = v_k.t + sum_m alpha_m d_m   (support function bound: any alpha >= 0
@@ -157,8 +171,7 @@ __device__ inline void dop18_cone(const double u[3], double alpha[3], int axis[3
 // with c_m = sign_m alpha_m and b the record's (lo, hi) array.  vtU/vtL
 // carry a pad covering every FP32 rounding of the bound's evaluation.
 template <int K>
-__device__ void pose_setup(const float *P, float maxA, float *coef, uint32_t *upidx, float *vtU, float *vtL,
-                           uint32_t lane)
+__device__ void pose_setup(const float *P, float maxA, float4 *xf, uint32_t lane)
 {
     if (lane >= (uint32_t)K) return;
     double R[3][3], t[3];
@@ -190,13 +203,13 @@ __device__ void pose_setup(const float *P, float maxA, float *coef, uint32_t *up
     double SA = (K == 9 ? 2.0 : 1.0) * (double)maxA * (1.0 + 0x1p-20);
     double pad = 8.0 * 0x1p-24 * (vn1 * tmax + asum * SA) + 0x1p-120;
     uint32_t packed = 0;
+    float c[3];
     for (int m = 0; m < 3; m++) {
-        coef[3 * lane + m] = (float)(sgn[m] * alpha[m]);
+        c[m] = (float)(sgn[m] * alpha[m]);
         packed |= (uint32_t)(2 * axis[m] + (sgn[m] > 0 ? 1 : 0)) << (8 * m);
     }
-    upidx[lane] = packed;
-    vtU[lane] = __double2float_ru(vt + pad);
-    vtL[lane] = __double2float_rd(vt - pad);
+    xf[2 * lane] = make_float4(c[0], c[1], c[2], __uint_as_float(packed));
+    xf[2 * lane + 1] = make_float4(__double2float_ru(vt + pad), __double2float_rd(vt - pad), 0.0f, 0.0f);
 }
 
 // Decode one node's 2K bounds (lo, hi per slab) from its parent's decoded
@@ -365,10 +378,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     const uint32_t lane = __lane_id();
     const Layout LY = make_layout(K, MODE, lim);
     unsigned char *base = lds_raw;
-    float *coef = (float *)(base + LY.coef);
-    uint32_t *upidx = (uint32_t *)(base + LY.upidx);
-    float *vtU = (float *)(base + LY.vtU);
-    float *vtL = (float *)(base + LY.vtL);
+    float4 *xf = (float4 *)(base + LY.xf);
     uint32_t *frame_end = (uint32_t *)(base + LY.frame_end);
     uint32_t *rtopo = (uint32_t *)(base + LY.rtopo);
     float *rbnd = (float *)(base + LY.rbnd);
@@ -380,7 +390,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     float *lq_lb = (float *)(base + LY.lq_lb);
     uint32_t *scratch = (uint32_t *)(base + LY.scratch);
     uint32_t *meta = (uint32_t *)(base + LY.meta);
-    uint4 *mpar = (uint4 *)(base + LY.mpar);
 
     constexpr uint32_t IW = words_of_item(K);
     constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass       // dwords per item
@@ -535,7 +544,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
                 P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
             }
-            pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, coef, upidx, vtU, vtL, lane);
+            pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, xf, lane);
             // distance: FP32 leaf-distance error bound, and the absolute
             // rounding allowance of the sphere bound
             e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
@@ -604,20 +613,27 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             if (have_frame) {
                 have_frame = false;
                 // -------- transform A's records of the frame into B's frame --------
-                // lane = (record c, slab my_k): CPL records per pass
-                const float my_c0 = coef[3 * my_k], my_c1 = coef[3 * my_k + 1], my_c2 = coef[3 * my_k + 2];
-                const uint32_t my_up = upidx[my_k];
-                const float my_vU = vtU[my_k], my_vL = vtL[my_k];
-                for (uint32_t c0 = 0; c0 < f_nA; c0 += CPL) {
-                    const uint32_t c = c0 + lane / (uint32_t)K;
-                    if (lane < CPL * (uint32_t)K && c < f_nA) {
-                        const float *b = rbnd + (size_t)(f_base + c) * 2 * K;
-                        const uint32_t i0 = my_up & 0xFFu, i1 = (my_up >> 8) & 0xFFu, i2 = (my_up >> 16) & 0xFFu;
-                        const float U = __builtin_fmaf(my_c2, b[i2], __builtin_fmaf(my_c1, b[i1], __builtin_fmaf(my_c0, b[i0], my_vU)));
-                        const float L =
-                            __builtin_fmaf(my_c2, b[i2 ^ 1u], __builtin_fmaf(my_c1, b[i1 ^ 1u], __builtin_fmaf(my_c0, b[i0 ^ 1u], my_vL)));
-                        ta[2 * K * c + 2 * my_k] = L;
-                        ta[2 * K * c + 2 * my_k + 1] = U;
+                // lane = (record c, slab my_k), CPL records per pass, two passes
+                // at a time; each generator reads its slab's (lo, hi) pair at once
+                {
+                    const float4 x0 = xf[2 * my_k], x1 = xf[2 * my_k + 1];
+                    const uint32_t up = __float_as_uint(x0.w);
+                    const uint32_t a0 = (up & 0xFFu) >> 1, a1 = ((up >> 8) & 0xFFu) >> 1, a2 = ((up >> 16) & 0xFFu) >> 1;
+                    const bool h0 = (up & 1u) != 0, h1 = (up & 0x100u) != 0, h2 = (up & 0x10000u) != 0;
+                    auto move = [&](uint32_t c, float2 p0, float2 p1, float2 p2) {
+                        // U takes each generator's hi for + signs (lo for -), L the other bound
+                        const float U = __builtin_fmaf(x0.z, h2 ? p2.y : p2.x,
+                                                       __builtin_fmaf(x0.y, h1 ? p1.y : p1.x, __builtin_fmaf(x0.x, h0 ? p0.y : p0.x, x1.x)));
+                        const float L = __builtin_fmaf(x0.z, h2 ? p2.x : p2.y,
+                                                       __builtin_fmaf(x0.y, h1 ? p1.x : p1.y, __builtin_fmaf(x0.x, h0 ? p0.x : p0.y, x1.y)));
+                        *(float2 *)(ta + 2 * K * c + 2 * my_k) = make_float2(L, U);
+                    };
+                    for (uint32_t c0 = 0; c0 < f_nA; c0 += CPL) {
+                        const uint32_t ca = c0 + lane / (uint32_t)K;
+                        if (lane < CPL * (uint32_t)K && ca < f_nA) {
+                            const float2 *b = (const float2 *)(rbnd + (size_t)(f_base + ca) * 2 * K);
+                            move(ca, b[a0], b[a1], b[a2]);
+                        }
                     }
                 }
                 if (MODE == MODE_DIST && lane < f_nA) {
@@ -642,7 +658,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     const uint32_t t = t0 + lane;
                     bool survive = false;
                     float lb = 0.0f;
-                    uint32_t recA = 0, recB = 0;
+                    uint32_t recA = 0, recB = 0, tA_w = 0, tB_w = 0;
                     if (t < f_tasks) {
                         // the task's entry: the last one whose first task is <= t
                         uint32_t w = mw[0];
@@ -655,6 +671,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         const uint32_t ia = aoff + i;
                         recA = f_base + ia;
                         recB = f_base + boff + j;
+                        // topology words load with the bounds (one LDS round trip)
+                        tA_w = rtopo[recA];
+                        tB_w = rtopo[recB];
                         const float *tA = ta + 2 * K * ia;
                         const float *bB = rbnd + (size_t)recB * 2 * K;
                         if (MODE == MODE_DIST) {
@@ -676,19 +695,20 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                             survive = lb <= tau;
                         } else {
                             bool sep = false;
+                            float ov = INFINITY;
 #pragma unroll
-                            for (int k = 0; k < K; k++) sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
+                            for (int k = 0; k < K; k++) {
+                                sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
+                                if (MODE == MODE_BOOL)
+                                    ov = fminf(ov, fminf(tA[2 * k + 1], bB[2 * k + 1]) - fmaxf(tA[2 * k], bB[2 * k]));
+                            }
                             survive = !sep;
+                            // early exit: the most deeply overlapping pair is expanded first
+                            lb = -ov;
                         }
                     }
                     // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
-                    uint32_t tA_w = 0, tB_w = 0;
-                    bool ll = false;
-                    if (survive) {
-                        tA_w = rtopo[recA];
-                        tB_w = rtopo[recB];
-                        ll = topo_leaf(tA_w) && topo_leaf(tB_w);
-                    }
+                    const bool ll = topo_leaf(tA_w) && topo_leaf(tB_w);
                     const uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
                     const uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
                     if (survive && ll) {
@@ -701,8 +721,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         ent[slot] = recA | (recB << REC_BITS) | (f_id << (2 * REC_BITS));
                         if (MODE == MODE_DIST) ent_lb[slot] = lb;
                     }
-                    if (MODE == MODE_DIST && n_nd > 0) {
-                        // remember the closest new node pair
+                    if ((MODE == MODE_DIST || MODE == MODE_BOOL) && n_nd > 0) {
+                        // remember the most promising new node pair: the closest
+                        // (distance) or the most deeply overlapping (collision)
                         const float mlb = wave_min((survive && !ll) ? lb : INFINITY);
                         if (mlb < near_lb) {
                             const uint64_t win = __ballot(survive && !ll && lb == mlb);
@@ -714,17 +735,19 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     lq_count += n_ll;
                     top += n_nd;
                 }
-                if (MODE == MODE_DIST && top - top0 > 1 && near_slot != top - 1) {
-                    // put the closest new pair on top of the stack
+                if ((MODE == MODE_DIST || MODE == MODE_BOOL) && top - top0 > 1 && near_slot != top - 1) {
+                    // put the most promising new pair on top of the stack
                     wave_sync();
                     if (lane == 0) {
                         const uint32_t last = top - 1;
                         const uint32_t e0 = ent[near_slot];
-                        const float l0 = ent_lb[near_slot];
                         ent[near_slot] = ent[last];
-                        ent_lb[near_slot] = ent_lb[last];
                         ent[last] = e0;
-                        ent_lb[last] = l0;
+                        if (MODE == MODE_DIST) {
+                            const float l0 = ent_lb[near_slot];
+                            ent_lb[near_slot] = ent_lb[last];
+                            ent_lb[last] = l0;
+                        }
                     }
                 }
                 cnt.bv_tests += f_tasks;
@@ -930,15 +953,14 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             const uint32_t my_tk = my_na * my_nb;
             const uint32_t my_pk = lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16)) : 0u;
             uint32_t pk = my_pk;
-#pragma unroll
-            for (int o = 1; o < PMAX; o <<= 1) {
-                const uint32_t x = __shfl_up(pk, o);
-                if (lane >= (uint32_t)o) pk += x;
-            }
+            static_assert(PMAX == 8, "the scan covers 8 lanes");
+            pk += row_shr<1>(pk);
+            pk += row_shr<2>(pk);
+            pk += row_shr<4>(pk);
             const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = pk >> 16;
             // with lane+1 entries popped the new frame sits on top of the frame of
             // the next remaining entry, which lane+1 has read
-            const uint32_t nx_e = __shfl_down(my_e, 1), nx_fend = __shfl_down(my_fend, 1);
+            const uint32_t nx_e = row_shl<1>(my_e), nx_fend = row_shl<1>(my_fend);
             const uint32_t rem_l = top - 1u - lane;
             const uint32_t nbase_l = rem_l > 0 ? nx_fend : 0u;
             const uint32_t nid_l = rem_l > 0 ? (nx_e >> (2 * REC_BITS)) + 1u : 0u;
@@ -979,7 +1001,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 const uint32_t ex = pk - my_pk;  // exclusive prefix
                 const uint32_t slot = mbcnt(m_act);
                 meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, ex >> 16);
-                mpar[slot] = make_uint4(my_e & REC_MASK, (my_e >> REC_BITS) & REC_MASK, my_pA, my_pB);
             }
             {
                 uint32_t nbytes = 0;
@@ -989,31 +1010,32 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 for (int o = 1; o < PMAX; o <<= 1) nbytes += __shfl_xor(nbytes, o);
                 cnt.node_bytes += lane_of(nbytes, 0);
             }
-            wave_sync();
             // decode: one lane per new record, A records first, then B records
             // (register staging: the new frame may overwrite the popped
-            // entries' own records)
+            // entries' own records).  A record's entry is the popped lane whose
+            // run of records holds it, found from the prefix words read as
+            // scalars; its parent data comes across lanes.
+            const bool sideA = lane < nA_tot;
+            const uint32_t r = sideA ? lane : lane - nA_tot;
+            uint32_t e = 0, off = 0;
+#pragma unroll
+            for (int s = 0; s < PMAX; s++) {
+                const uint32_t w = lane_of(pk, s);
+                const uint32_t end = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
+                if ((uint32_t)s < n_pop && end <= r) {
+                    e = (uint32_t)s + 1u;
+                    off = end;
+                }
+            }
+            e = min(e, (uint32_t)PMAX - 1u);
+            const uint32_t g_pA = gather(my_pA, e), g_pB = gather(my_pB, e), g_e = gather(my_e, e);
             uint32_t my_topo = 0;
             float my_b[2 * K];
             const bool dec = lane < total_rec;
             if (dec) {
-                const bool sideA = lane < nA_tot;
-                uint32_t e = 0, off = sideA ? 0u : nA_tot;
-#pragma unroll
-                for (int s = 1; s < PMAX; s++) {
-                    if ((uint32_t)s < ns) {
-                        const uint32_t w = meta[s];
-                        const uint32_t o = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
-                        if (lane >= o) {
-                            e = (uint32_t)s;
-                            off = o;
-                        }
-                    }
-                }
-                const uint4 pr = mpar[e];
-                const uint32_t c = lane - off;
-                const uint32_t prec = sideA ? pr.x : pr.y;
-                const uint32_t ptopo = sideA ? pr.z : pr.w;
+                const uint32_t c = r - off;
+                const uint32_t prec = sideA ? (g_e & REC_MASK) : ((g_e >> REC_BITS) & REC_MASK);
+                const uint32_t ptopo = sideA ? g_pA : g_pB;
                 const float *pb = rbnd + (size_t)prec * 2 * K;
                 if (topo_leaf(ptopo)) {
                     my_topo = ptopo;
