@@ -262,10 +262,17 @@ def main():
             "bv_test_inflation": main_s["bv_tests_per_call"] / max(1, out["uncompressed"]["bv_tests_per_call"]),
             "speedup_vs_fp32": main_s["poses_per_sec"] / out["uncompressed"]["poses_per_sec"],
         }
+        # the paper's half-precision descriptors (section III.A), a third point
+        f16 = run_collide(cb, w, cb.BITS_FP16, dev, args.steps, args.warmup, cb.EARLY_EXIT)
+        out["fp16"] = summarize(f16, args.steps)
+        out["fp16"]["hits_equal"] = f16["hits"] == main_r["hits"]
+        out["compression"]["descriptor_bytes_fp16"] = out["fp16"]["descriptor_bytes"]
+        out["compression"]["bv_test_inflation_fp16"] = (out["fp16"]["bv_tests_per_call"] /
+                                                        max(1, out["uncompressed"]["bv_tests_per_call"]))
         w0, w2 = configs.WORKLOADS[0], configs.WORKLOADS[2]
         tiny = run_collide(cb, w0, w0.bits, dev, 10, 2, cb.PAIRS, pair_capacity=1 << 20)
         out["tiny_pairs"] = summarize(tiny, 10)
-        for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32")):
+        for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
             pr = run_distance(cb, w2, bits, dev, 5, 1)
             out[key] = summarize(pr, 5)
     if not args.no_cpu:

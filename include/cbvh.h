@@ -55,6 +55,12 @@ typedef enum {
 
 typedef enum { CBVH_AABB = 0, CBVH_DOP18 = 1 } cbvh_bv;
 
+/* `bits` value selecting absolute binary16 descriptors, each bound rounded
+ * outward (lo down, hi up): the half-precision BVs of section III.A of the
+ * paper, a third comparison point beside FP32 and the corrector codes.
+ * Needs every |coordinate| < 32768 (18-DOP: < 16384); 4 bytes per slab. */
+#define CBVH_BITS_FP16 0x8010u
+
 /* Build parameters.  Table I of the paper lists the descriptor sizes
  * (AABB 6 floats, k-DOP k floats); `bits` selects the quantized width. */
 typedef struct {
@@ -62,7 +68,8 @@ typedef struct {
     uint32_t bv;            /* CBVH_AABB (3 slabs) or CBVH_DOP18 (9 slabs) */
     uint32_t branching;     /* children per inner node: 2, 4 or 8 */
     uint32_t leaf_size;     /* triangles per leaf: 1..8 */
-    uint32_t bits;          /* 0 = FP32 descriptors (uncompressed), 8 or 16 = quantized codes */
+    uint32_t bits;          /* 0 = FP32 descriptors (uncompressed), 8 or 16 = quantized codes,
+                               CBVH_BITS_FP16 = half-precision descriptors */
     uint32_t treelet_bytes; /* byte budget of one treelet; 0 = default (8192); >= 256 otherwise */
 } cbvh_build_params;
 

@@ -857,7 +857,9 @@ EXPORT void orc_classify_batch(const void *A, const void *B, const float *poses,
  *   topo[n]: u32; bit31 leaf, bit30 absolute, bits27-29 count-1,
  *     bits0-26 first child node (inner) or first leaf-order triangle (leaf).
  *   codes[n][code_stride]: per slab (lo code, hi code), u8 or u16; with
- *     bits = 0, (lo, hi) as f32.  Absolute nodes keep a u32 index into abs.
+ *     bits = 0, (lo, hi) as f32; with bits = 0x8010, (lo, hi) as IEEE
+ *     binary16 (the half-precision descriptors of section III.A of the
+ *     paper, rounded outward).  Absolute nodes keep a u32 index into abs.
  *   abs[n_abs][2K]: f32 (lo, hi) per slab.
  *   tris[n_tris][9]: f32 in leaf order;  perm[n_tris]: u32 input index.
  *   treelets[n_treelets+1]: u32 first node of each treelet.
@@ -875,6 +877,21 @@ static uint64_t rd64(const uint8_t *p) { return (uint64_t)rd32(p) | (uint64_t)rd
 static float rdf32(const uint8_t *p) { uint32_t u = rd32(p); float f; memcpy(&f, &u, 4); return f; }
 static uint16_t rd16(const uint8_t *p) { return (uint16_t)(p[0] | p[1] << 8); }
 
+#define BITS_FP16 0x8010u
+static int bits_codes(uint32_t b) { return b == 8 || b == 16; }
+/* IEEE binary16 -> float, exactly: subnormals m * 2^-24, normals
+ * (1024 + m) * 2^(e - 25); exponent 31 (inf / NaN) is not a valid bound */
+static int half_finite(uint16_t h) { return ((h >> 10) & 31) != 31; }
+static float half_value(uint16_t h)
+{
+    int e = (h >> 10) & 31, m = h & 1023;
+    float v = e == 0 ? ldexpf((float)m, -24) : ldexpf((float)(m | 1024), e - 25);
+    return (h & 0x8000) ? -v : v;
+}
+/* neighbouring binary16 values towards +inf / -inf */
+static uint16_t half_next_up(uint16_t h) { return h == 0x8000 ? 0x0001 : (h & 0x8000) ? (uint16_t)(h - 1) : (uint16_t)(h + 1); }
+static uint16_t half_next_down(uint16_t h) { return h == 0x0000 ? 0x8001 : (h & 0x8000) ? (uint16_t)(h + 1) : (uint16_t)(h - 1); }
+
 static int parse_header(const uint8_t *blob, size_t n, ohdr_t *h, char *msg, size_t ml)
 {
     if (n < 128 || memcmp(blob, "CBVH", 4) != 0) { snprintf(msg, ml, "bad magic/size"); return -1; }
@@ -885,8 +902,8 @@ static int parse_header(const uint8_t *blob, size_t n, ohdr_t *h, char *msg, siz
     h->off_topo = rd64(blob + 56); h->off_codes = rd64(blob + 64); h->off_abs = rd64(blob + 72); h->off_tris = rd64(blob + 80);
     h->off_perm = rd64(blob + 88); h->off_treelets = rd64(blob + 96); h->total = rd64(blob + 104); h->max_abs_coord = rdf32(blob + 112);
     if (!((h->bv == 0 && h->K == 3) || (h->bv == 1 && h->K == 9))) { snprintf(msg, ml, "bad bv/K"); return -1; }
-    if (!(h->bits == 0 || h->bits == 8 || h->bits == 16)) { snprintf(msg, ml, "bad bits"); return -1; }
-    uint32_t want = h->bits == 0 ? 8 * h->K : (h->bits / 8) * 2 * h->K;
+    if (!(h->bits == 0 || bits_codes(h->bits) || h->bits == BITS_FP16)) { snprintf(msg, ml, "bad bits"); return -1; }
+    uint32_t want = h->bits == 0 ? 8 * h->K : h->bits == BITS_FP16 ? 4 * h->K : (h->bits / 8) * 2 * h->K;
     if (h->code_stride != want) { snprintf(msg, ml, "bad code stride"); return -1; }
     if (h->total != n) { snprintf(msg, ml, "size mismatch"); return -1; }
 #define FITS(off, bytes) ((off) <= n && (uint64_t)(bytes) <= n - (off))
@@ -912,6 +929,13 @@ static int decode_all(const uint8_t *blob, const ohdr_t *h, float *out, int32_t 
         int absolute = (tw >> 30) & 1;
         if (h->bits == 0) {
             for (uint32_t k = 0; k < K2; k++) out[K2 * (size_t)i + k] = rdf32(code + 4 * k);
+        } else if (h->bits == BITS_FP16) {
+            if (absolute) { snprintf(msg, ml, "absolute flag in an FP16 blob"); return -1; }
+            for (uint32_t k = 0; k < K2; k++) {
+                uint16_t hv = rd16(code + 2 * k);
+                if (!half_finite(hv)) { snprintf(msg, ml, "non-finite FP16 bound at node %u", i); return -1; }
+                out[K2 * (size_t)i + k] = half_value(hv);
+            }
         } else if (absolute || parent[i] < 0) {
             if (!absolute) { snprintf(msg, ml, "root not absolute"); return -1; }
             uint32_t ai = rd32(code);
@@ -1078,7 +1102,11 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
             float lo = dec[K2 * (size_t)i + 2 * k], hi = dec[K2 * (size_t)i + 2 * k + 1];
             dd_t el = exlo[h.K * (size_t)i + k], eh = exhi[h.K * (size_t)i + k];
             if (!f_le_dd(lo, el) || !f_ge_dd(hi, eh)) { snprintf(msg, ml, "node %u slab %u does not enclose", i, k); goto done; }
-            if (h.bits == 0 || absolute) {
+            if (h.bits == BITS_FP16) {
+                /* binary16 bounds: tightest halves, i.e. the next half inward fails */
+                float lo2 = half_value(half_next_up(rd16(code + 4 * k))), hi2 = half_value(half_next_down(rd16(code + 4 * k + 2)));
+                if (f_le_dd(lo2, el) || f_ge_dd(hi2, eh)) { snprintf(msg, ml, "node %u slab %u FP16 bound not tight", i, k); goto done; }
+            } else if (h.bits == 0 || absolute) {
                 /* absolute bounds: tightest floats, i.e. the next float inward fails */
                 float lo2 = nextafterf(lo, INFINITY), hi2 = nextafterf(hi, -INFINITY);
                 if (f_le_dd(lo2, el) || f_ge_dd(hi2, eh)) { snprintf(msg, ml, "node %u slab %u absolute bound not tight", i, k); goto done; }
@@ -1086,7 +1114,7 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
             if (parent[i] >= 0) {
                 const float *P = &dec[K2 * (size_t)parent[i]];
                 if (lo < P[2 * k] || hi > P[2 * k + 1]) { snprintf(msg, ml, "node %u slab %u outside parent", i, k); goto done; }
-                if (h.bits && !absolute) {
+                if (bits_codes(h.bits) && !absolute) {
                     uint32_t ql, qh, Q = (1u << h.bits) - 1;
                     if (h.bits == 8) { ql = code[2 * k]; qh = code[2 * k + 1]; }
                     else { ql = rd16(code + 4 * k); qh = rd16(code + 4 * k + 2); }
@@ -1116,11 +1144,11 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
             uint32_t tw = rd32(blob + h.off_topo + 4ull * i);
             int absolute = (tw >> 30) & 1;
             int top = parent[i] < 0 || treelet_of[parent[i]] != treelet_of[i];
-            if (h.bits == 0) { if (absolute) { snprintf(msg, ml, "absolute flag in uncompressed blob"); goto done; } continue; }
+            if (!bits_codes(h.bits)) { if (absolute) { snprintf(msg, ml, "absolute flag in a blob without codes"); goto done; } continue; }
             if (absolute != top) { snprintf(msg, ml, "node %u absolute flag %d but treelet top %d", i, absolute, top); goto done; }
             n_abs += (uint32_t)absolute;
         }
-        if (h.bits && n_abs != h.n_abs) { snprintf(msg, ml, "n_abs mismatch"); goto done; }
+        if (bits_codes(h.bits) && n_abs != h.n_abs) { snprintf(msg, ml, "n_abs mismatch"); goto done; }
     }
     rc = 0;
 done:

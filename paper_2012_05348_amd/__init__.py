@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbvh.so")
 
 AABB, DOP18 = 0, 1
+BITS_FP16 = 0x8010  # half-precision absolute descriptors (CBVH_BITS_FP16)
 EARLY_EXIT, PAIRS, NO_SPLIT = 0x1, 0x2, 0x4
 POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_CAPACITY", 5: "E_UNSUPPORTED", 6: "E_FORMAT"}

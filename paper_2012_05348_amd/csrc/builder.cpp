@@ -169,6 +169,39 @@ struct Builder {
     }
 };
 
+// binary16 helpers for the half-precision descriptors: finite halves in
+// value order are ranks 0 .. 2*0x7C00-1 (negatives from -65504 up to -0,
+// then +0 up to +65504)
+constexpr uint32_t kHalfRanks = 2u * 0x7C00u;
+uint16_t half_of_rank(uint32_t r) { return r < 0x7C00u ? (uint16_t)(0x8000u | (0x7BFFu - r)) : (uint16_t)(r - 0x7C00u); }
+double half_value(uint16_t h)
+{
+    const int e = (h >> 10) & 0x1F, m = h & 0x3FF;
+    const double v = e == 0 ? std::ldexp((double)m, -24) : std::ldexp((double)(m | 0x400), e - 25);
+    return (h & 0x8000u) ? -v : v;
+}
+inline bool d_le(double d, const Exact &v) { return d < v.s || (d == v.s && v.e >= 0.0); }
+inline bool d_ge(double d, const Exact &v) { return d > v.s || (d == v.s && v.e <= 0.0); }
+// largest half <= v, smallest half >= v (v within the finite half range)
+uint16_t half_down(const Exact &v)
+{
+    uint32_t lo = 0, hi = kHalfRanks - 1;  // invariant: value(lo) <= v
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) / 2;
+        if (d_le(half_value(half_of_rank(mid)), v)) lo = mid; else hi = mid - 1;
+    }
+    return half_of_rank(lo);
+}
+uint16_t half_up(const Exact &v)
+{
+    uint32_t lo = 0, hi = kHalfRanks - 1;  // invariant: value(hi) >= v
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (d_ge(half_value(half_of_rank(mid)), v)) hi = mid; else lo = mid + 1;
+    }
+    return half_of_rank(hi);
+}
+
 // b-bit corrector codes of one slab relative to the decoded parent
 // [Pl, Ph]: the largest codes whose decoded bounds still enclose [cl, ch]
 void encode_slab(float Pl, float Ph, const Exact &cl, const Exact &ch, uint32_t bits, uint32_t *ql, uint32_t *qh,
@@ -243,7 +276,10 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
     // Every cut group becomes the top group of its own treelet and stores its
     // bounds absolute; the budget of the relative parts leaves room for that.
     const uint64_t rel_node = 4 + stride;
-    const uint64_t abs_node = p.bits ? 4 + stride + 8 * (uint64_t)K : 4 + stride;
+    const bool codes_mode = bits_are_codes(p.bits);
+    if (p.bits == kBitsFp16 && max_abs * (K == 9 ? 2.0f : 1.0f) >= 32768.0f)
+        return "FP16 descriptors need |coordinate| < 32768 (16384 for 18-DOPs)";
+    const uint64_t abs_node = codes_mode ? 4 + stride + 8 * (uint64_t)K : 4 + stride;
     std::vector<std::vector<uint32_t>> groups;   // node ids per group, breadth-first
     std::vector<std::vector<uint32_t>> kids;     // child groups of each group
     groups.push_back({0u});
@@ -319,7 +355,7 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
     for (uint32_t i = 0; i < n_nodes; i++) {
         const TmpNode &nd = B.nodes[oldid[i]];
         depth = std::max(depth, nd.depth);
-        bool absolute = p.bits && is_top[oldid[i]];
+        bool absolute = codes_mode && is_top[oldid[i]];
         if (absolute) abs_index[i] = n_abs++;
         if (nd.leaf) {
             uint32_t first = (uint32_t)perm.size();
@@ -348,6 +384,16 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
         const TmpNode &nd = B.nodes[oldid[i]];
         float *d = &dec[(size_t)i * 2 * Kc];
         uint8_t *code = &codes[(size_t)i * stride];
+        if (p.bits == kBitsFp16) {
+            for (uint32_t k = 0; k < Kc; k++) {
+                uint16_t a = half_down(nd.lo[k]), b = half_up(nd.hi[k]);
+                memcpy(code + 4 * k, &a, 2);
+                memcpy(code + 4 * k + 2, &b, 2);
+                d[2 * k] = (float)half_value(a);
+                d[2 * k + 1] = (float)half_value(b);
+            }
+            continue;
+        }
         if (p.bits == 0 || topo_abs(topo[i])) {
             for (uint32_t k = 0; k < Kc; k++) {
                 d[2 * k] = round_down(nd.lo[k]);
@@ -433,7 +479,7 @@ std::string validate_blob(const uint8_t *blob, size_t n, BlobHeader *hp, uint32_
     memcpy(&h, blob, sizeof h);
     if (h.magic != kMagic || h.version != kVersion) return "bad magic or version";
     if (!((h.bv == 0 && h.K == 3) || (h.bv == 1 && h.K == 9))) return "bad BV type";
-    if (!(h.bits == 0 || h.bits == 8 || h.bits == 16)) return "bad code width";
+    if (!(h.bits == 0 || bits_are_codes(h.bits) || h.bits == kBitsFp16)) return "bad code width";
     if (!(h.branching == 2 || h.branching == 4 || h.branching == 8)) return "bad branching factor";
     if (h.leaf_size < 1 || h.leaf_size > kMaxLeaf) return "bad leaf size";
     if (h.code_stride != code_stride_for(h.K, h.bits)) return "bad code stride";
@@ -455,11 +501,11 @@ std::string validate_blob(const uint8_t *blob, size_t n, BlobHeader *hp, uint32_
         uint32_t w = topo[i];
         max_depth = std::max(max_depth, depth[i]);
         if (topo_abs(w)) {
-            if (h.bits == 0) return "absolute flag in an uncompressed model";
+            if (!bits_are_codes(h.bits)) return "absolute flag in a model without codes";
             uint32_t ai;
             memcpy(&ai, blob + h.off_codes + (uint64_t)h.code_stride * i, 4);
             if (ai >= h.n_abs) return "absolute index out of range";
-        } else if (i == 0 && h.bits != 0) {
+        } else if (i == 0 && bits_are_codes(h.bits)) {
             return "root not absolute";
         }
         uint32_t first = topo_first(w), cnt = topo_count(w);

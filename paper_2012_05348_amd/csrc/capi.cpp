@@ -190,7 +190,8 @@ cbvh_status cbvh_build(const float *V, uint32_t nv, const uint32_t *T, uint32_t 
         if (!(params->branching == 2 || params->branching == 4 || params->branching == 8))
             return fail(CBVH_E_INVALID, "branching must be 2, 4 or 8");
         if (params->leaf_size < 1 || params->leaf_size > cbvh::kMaxLeaf) return fail(CBVH_E_INVALID, "leaf_size must be 1..8");
-        if (!(params->bits == 0 || params->bits == 8 || params->bits == 16)) return fail(CBVH_E_INVALID, "bits must be 0, 8 or 16");
+        if (!(params->bits == 0 || params->bits == 8 || params->bits == 16 || params->bits == CBVH_BITS_FP16))
+            return fail(CBVH_E_INVALID, "bits must be 0, 8, 16 or CBVH_BITS_FP16");
         uint32_t tb = params->treelet_bytes ? params->treelet_bytes : 8192u;
         if (tb < 256) return fail(CBVH_E_INVALID, "treelet_bytes must be 0 or >= 256");
         cbvh::BuildParams p{params->bv, params->branching, params->leaf_size, params->bits, tb};

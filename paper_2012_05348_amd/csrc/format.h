@@ -14,7 +14,9 @@
 //
 // Codes per slab k (slab directions: x, y, z for AABB; plus x+y, x+z, y+z,
 // x-y, x-z, y-z for the 18-DOP): (lo code, hi code) as u8 or u16; with
-// bits == 0 the slot holds absolute (lo, hi) float32 bounds instead.
+// bits == 0 the slot holds absolute (lo, hi) float32 bounds instead, and
+// with bits == kBitsFp16 absolute (lo, hi) binary16 bounds rounded outward
+// (the half-precision descriptors of the paper's section III.A).
 //
 // Decode of a relative node from its decoded parent [Pl, Ph] (per slab):
 //   E = Ph - Pl (float32),  s = (E >= 2^-100) ? E * 2^-bits : 0,
@@ -62,6 +64,14 @@ CBVH_HD inline uint32_t make_topo(uint32_t first, uint32_t count, bool leaf, boo
     return (first & kIndexMask) | ((count - 1u) << 27) | (absolute ? kAbsBit : 0u) | (leaf ? kLeafBit : 0u);
 }
 
-inline uint32_t code_stride_for(uint32_t K, uint32_t bits) { return bits == 0 ? 8u * K : (bits / 8u) * 2u * K; }
+// `bits` value of models with binary16 absolute descriptors
+constexpr uint32_t kBitsFp16 = 0x8010u;
+// integer corrector codes relative to the parent (8 or 16 bits)?
+CBVH_HD inline bool bits_are_codes(uint32_t bits) { return bits == 8u || bits == 16u; }
+
+inline uint32_t code_stride_for(uint32_t K, uint32_t bits)
+{
+    return bits == 0 ? 8u * K : bits == kBitsFp16 ? 4u * K : (bits / 8u) * 2u * K;
+}
 
 }  // namespace cbvh

@@ -98,6 +98,8 @@ struct QueryArgs {
     uint32_t max_pop;   // entries one node step may pop (1..8)
     uint32_t donate_min_steps;  // a unit feeds waiting waves only after this many steps
     uint32_t max_helpers;       // waves that stay to take items once the poses are gone
+    uint32_t donate_period;     // node steps between two looks at the item queue
+    uint32_t donate_keep;       // entries a donor keeps at least (0 = half of its stack)
     Workspace ws;
 };
 

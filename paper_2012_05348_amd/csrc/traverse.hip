@@ -215,13 +215,21 @@ __device__ void pose_setup(const float *P, float maxA, float4 *xf, uint32_t lane
 // Decode one node's 2K bounds (lo, hi per slab) from its parent's decoded
 // bounds: E = Ph - Pl, s = E * 2^-BITS (0 if E < 2^-100), lo = fma(ql, s, Pl),
 // hi = fma(-qh, s, Ph).  Absolute nodes (treelet tops) and uncompressed
-// models read FP32 bounds instead.
+// models read FP32 bounds instead, half-precision models binary16 bounds.
 template <int K, int BITS, typename ParentPtr>
 __device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, uint32_t topo, ParentPtr parent,
                                             float out[2 * K])
 {
     const uint8_t *code = M.codes + (size_t)node * M.stride;
-    if (BITS == 0) {
+    if constexpr (BITS == (int)kBitsFp16) {
+        // binary16 absolute bounds, widened exactly
+        const _Float16 *h = (const _Float16 *)code;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            out[2 * k] = (float)h[2 * k];
+            out[2 * k + 1] = (float)h[2 * k + 1];
+        }
+    } else if constexpr (BITS == 0) {
         const float2 *c = (const float2 *)code;
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -239,7 +247,7 @@ __device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, ui
             out[2 * k + 1] = w.y;
         }
     } else {
-        const float scale = 1.0f / (float)(1u << BITS);
+        const float scale = 1.0f / (float)(1u << (BITS & 31));
 #pragma unroll
         for (int k = 0; k < K; k++) {
             uint32_t ql, qh;
@@ -903,12 +911,13 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
 
             // -------- feed waiting waves with the bottom of the stack --------
             if (can_donate && top >= 2 && steps >= next_look && steps >= q.donate_min_steps) {
-                next_look = steps + kDonatePeriod;
+                next_look = steps + q.donate_period;
                 uint32_t want = 0;
                 if (lane == 0) {
                     unsigned long long ht = poll64((unsigned long long *)&hdr->q_head);
                     uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
-                    want = h > t ? min(h - t, min(top / 2, kMaxDonate)) : 0u;
+                    const uint32_t share = q.donate_keep ? (top > q.donate_keep ? top - q.donate_keep : 0u) : top / 2;
+                    want = h > t ? min(h - t, min(share, kMaxDonate)) : 0u;
                 }
                 want = uni(want);
                 if (want && publish(pose, want, want, best32) == want) {
@@ -1307,10 +1316,11 @@ template <int K, int BITS>
 __global__ void decode_all_kernel(DevModel M, float *out)
 {
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (BITS == 0) {
+    if (!bits_are_codes((uint32_t)BITS)) {
+        // absolute descriptors (FP32 or FP16): one thread per node
         for (uint32_t i = t; i < M.n_nodes; i += gridDim.x * blockDim.x) {
             float b[2 * K];
-            decode_node<K, 0>(M, i, M.topo[i], (const float *)nullptr, b);
+            decode_node<K, BITS>(M, i, M.topo[i], (const float *)nullptr, b);
             for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
         }
         return;
@@ -1382,6 +1392,8 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     qq.max_pop = min(env_u32("CBVH_MAX_POP", (uint32_t)PMAX), (uint32_t)PMAX);
     qq.donate_min_steps = env_u32("CBVH_DONATE_MIN_STEPS", kDonateMinSteps);
     qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * kHelpersPerCu);
+    qq.donate_period = env_u32("CBVH_DONATE_PERIOD", kDonatePeriod);
+    qq.donate_keep = env_u32("CBVH_DONATE_KEEP", 1u) == 1u ? 0u : env_u32("CBVH_DONATE_KEEP", 1u);
     hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, qq, lim);
     return hipGetLastError();
 }
@@ -1399,13 +1411,16 @@ hipError_t launch_mode(const QueryArgs &q, const StackLimits &lim, hipStream_t s
 hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
     uint32_t K = q.A.K, bits = q.A.bits;
+    constexpr int F16 = (int)kBitsFp16;
     if (K == 3) {
         if (bits == 0) return launch_mode<3, 0>(q, lim, s);
         if (bits == 8) return launch_mode<3, 8>(q, lim, s);
+        if (bits == kBitsFp16) return launch_mode<3, F16>(q, lim, s);
         return launch_mode<3, 16>(q, lim, s);
     }
     if (bits == 0) return launch_mode<9, 0>(q, lim, s);
     if (bits == 8) return launch_mode<9, 8>(q, lim, s);
+    if (bits == kBitsFp16) return launch_mode<9, F16>(q, lim, s);
     return launch_mode<9, 16>(q, lim, s);
 }
 
@@ -1470,15 +1485,18 @@ hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t 
 hipError_t launch_decode_all(const DevModel &m, float *out, hipStream_t s)
 {
     uint32_t threads = 64;
-    uint32_t items = m.bits == 0 ? m.n_nodes : m.n_treelets;
+    uint32_t items = bits_are_codes(m.bits) ? m.n_treelets : m.n_nodes;
+    constexpr int F16 = (int)kBitsFp16;
     dim3 grid((items + threads - 1) / threads);
     if (m.K == 3) {
         if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<3, 0>), grid, dim3(threads), 0, s, m, out);
         else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<3, 8>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == kBitsFp16) hipLaunchKernelGGL((decode_all_kernel<3, F16>), grid, dim3(threads), 0, s, m, out);
         else hipLaunchKernelGGL((decode_all_kernel<3, 16>), grid, dim3(threads), 0, s, m, out);
     } else {
         if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<9, 0>), grid, dim3(threads), 0, s, m, out);
         else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<9, 8>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == kBitsFp16) hipLaunchKernelGGL((decode_all_kernel<9, F16>), grid, dim3(threads), 0, s, m, out);
         else hipLaunchKernelGGL((decode_all_kernel<9, 16>), grid, dim3(threads), 0, s, m, out);
     }
     return hipGetLastError();

@@ -21,7 +21,7 @@ def topo_word(first, count, leaf=False, absolute=False):
 def assemble(bv, bits, branching, leaf_size, topo, codes, abs_bounds, tris, perm, treelets, depth=0,
              treelet_bytes=0, max_abs_coord=0.0):
     K = 3 if bv == 0 else 9
-    stride = 8 * K if bits == 0 else (bits // 8) * 2 * K
+    stride = 8 * K if bits == 0 else 4 * K if bits == 0x8010 else (bits // 8) * 2 * K
     topo = np.asarray(topo, dtype=np.uint32)
     codes = np.asarray(codes, dtype=np.uint8).reshape(len(topo), stride)
     abs_bounds = np.asarray(abs_bounds, dtype=np.float32).reshape(-1, 2 * K)

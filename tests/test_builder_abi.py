@@ -28,12 +28,12 @@ def mesh_sets():
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 2])
-@pytest.mark.parametrize("compressed", [True, False])
-def test_invariants_on_workload_meshes(cfg, compressed, mesh_sets):
+@pytest.mark.parametrize("fmt", ["codes", "fp32", "fp16"])
+def test_invariants_on_workload_meshes(cfg, fmt, mesh_sets):
     w = configs.WORKLOADS[cfg]
+    bits = {"codes": w.bits, "fp32": 0, "fp16": cb.BITS_FP16}[fmt]
     for V, T in mesh_sets[cfg]:
-        h = cb.cbvh_build(V, T, bv=BV[w.bv], branching=w.branching, leaf_size=w.leaf_size,
-                          bits=w.bits if compressed else 0)
+        h = cb.cbvh_build(V, T, bv=BV[w.bv], branching=w.branching, leaf_size=w.leaf_size, bits=bits)
         blob = cb.cbvh_blob(h)
         assert oracle.blob_check(blob, V, T) is None
         cb.cbvh_free(h)
@@ -41,7 +41,8 @@ def test_invariants_on_workload_meshes(cfg, compressed, mesh_sets):
 
 @pytest.mark.parametrize("bv,bf,leaf,bits,tb", [
     (cb.AABB, 2, 1, 8, 256), (cb.AABB, 8, 8, 16, 0), (cb.DOP18, 4, 2, 8, 1024), (cb.DOP18, 2, 3, 16, 4096),
-    (cb.DOP18, 8, 1, 0, 0), (cb.AABB, 4, 5, 0, 512)])
+    (cb.DOP18, 8, 1, 0, 0), (cb.AABB, 4, 5, 0, 512), (cb.DOP18, 8, 4, cb.BITS_FP16, 0),
+    (cb.AABB, 2, 1, cb.BITS_FP16, 256)])
 def test_invariants_parameter_sweep(bv, bf, leaf, bits, tb):
     V, T = meshes.torus(40, 12, 1.0, 0.3, 0.02, np.random.default_rng(3))
     h = cb.cbvh_build(V, T, bv=bv, branching=bf, leaf_size=leaf, bits=bits, treelet_bytes=tb)
@@ -71,7 +72,7 @@ def test_topology_shared_by_all_descriptor_formats():
     V, T = meshes.icosphere(6, 0.1, np.random.default_rng(1))
     ref = None
     for bv in (cb.AABB, cb.DOP18):
-        for bits in (0, 8, 16):
+        for bits in (0, 8, 16, cb.BITS_FP16):
             h = cb.cbvh_build(V, T, bv=bv, branching=4, leaf_size=2, bits=bits, treelet_bytes=1 << 20)
             t = _topo(cb.cbvh_blob(h))
             if ref is None:
@@ -139,6 +140,35 @@ def test_checker_catches_a_wrong_uncompressed_bound():
     hi = struct.unpack_from("<f", blob, pos)[0]
     struct.pack_into("<f", blob, pos, np.nextafter(np.float32(hi), np.float32(-np.inf)))
     assert "enclose" in oracle.blob_check(bytes(blob), V, T)
+
+
+@pytest.mark.parametrize("which", ["lo_inward", "hi_inward", "lo_outward"])
+def test_checker_catches_wrong_fp16_bounds(which):
+    # FP16 bounds are the tightest halves enclosing the exact slab: one half
+    # inward breaks enclosure, one half outward breaks tightness
+    blob, V, T = _small_blob(bits=cb.BITS_FP16)
+    off_codes = struct.unpack_from("<Q", blob, 64)[0]
+    stride = oracle.blob_info(bytes(blob))["code_stride"]
+    pos = off_codes + 4 * stride + (2 if which == "hi_inward" else 0)   # node 4, slab x
+    h = struct.unpack_from("<H", blob, pos)[0]
+    up = which in ("lo_inward",)
+    step = lambda x, u: (x + 1 if not (x & 0x8000) else x - 1) if u else (x - 1 if not (x & 0x8000) else x + 1)
+    if which == "lo_outward":
+        up = False
+    if h in (0x0000, 0x8000):
+        pytest.skip("zero bound")
+    struct.pack_into("<H", blob, pos, step(h, up))
+    msg = oracle.blob_check(bytes(blob), V, T)
+    assert msg is not None and ("enclose" in msg or "tight" in msg or "parent" in msg), msg
+
+
+def test_fp16_needs_coordinates_in_half_range():
+    V, T = meshes.icosphere(2, 0.1, np.random.default_rng(0))
+    cb.cbvh_free(cb.cbvh_build(V * 25000.0, T, bits=cb.BITS_FP16))           # AABB: < 32768
+    with pytest.raises(cb.CbvhError):
+        cb.cbvh_build(V * 40000.0, T, bits=cb.BITS_FP16)
+    with pytest.raises(cb.CbvhError):
+        cb.cbvh_build(V * 20000.0, T, bv=cb.DOP18, bits=cb.BITS_FP16)        # 18-DOP: < 16384
 
 
 # ---- blob validation (cbvh_load) ---------------------------------------------------

@@ -36,7 +36,9 @@ def _log(msg):
 def _models(cfg, compressed=True, **over):
     w = configs.WORKLOADS[cfg]
     (va, ta), (vb, tb) = W.meshes(cfg)
-    kw = dict(bv=W.BV[w.bv], branching=w.branching, leaf_size=w.leaf_size, bits=w.bits if compressed else 0)
+    # compressed: True = corrector codes, False = FP32, "fp16" = half-precision descriptors
+    bits = cb.BITS_FP16 if compressed == "fp16" else (w.bits if compressed else 0)
+    kw = dict(bv=W.BV[w.bv], branching=w.branching, leaf_size=w.leaf_size, bits=bits)
     kw.update(over)
     return cb.Model.build(va, ta, **kw).to(DEV), cb.Model.build(vb, tb, **kw).to(DEV)
 
@@ -53,7 +55,7 @@ def models(cfg, compressed=True):
 
 # ---------------------------------------------------------------- decode
 @pytest.mark.parametrize("cfg", [0, 1, 2])
-@pytest.mark.parametrize("compressed", [True, False])
+@pytest.mark.parametrize("compressed", [True, False, "fp16"])
 def test_decode_all_bit_exact(cfg, compressed):
     _log(f"decode cfg={cfg} compressed={compressed}")
     for m in models(cfg, compressed):
@@ -68,7 +70,7 @@ def _pairs_per_pose(pairs, offs, n):
     return [pairs[offs[i]:offs[i + 1]] for i in range(n)]
 
 
-@pytest.mark.parametrize("compressed", [True, False])
+@pytest.mark.parametrize("compressed", [True, False, "fp16"])
 def test_tiny_pairs_match_oracle(compressed):
     P, _ = W.config0_poses()
     A, B = W.oracle_meshes(0)
@@ -108,7 +110,7 @@ def scaled_results():
     P = w.raw_poses()
     Pd = torch.from_numpy(P).to(DEV)
     out = {}
-    for compressed in (True, False):
+    for compressed in (True, False, "fp16"):
         ma, mb = models(1, compressed)
         _log(f"scaled collide compressed={compressed}")
         ws = cb.workspace(ma, mb, len(P))
@@ -128,7 +130,7 @@ def test_scaled_booleans_match_oracle_on_sample(scaled_results):
     keep = idx[cls != oracle.MARGINAL]
     assert len(keep) > 200
     ref, _ = oracle.collide_batch(A, B, P[keep])
-    for compressed in (True, False):
+    for compressed in (True, False, "fp16"):
         hit, st, _ = out[compressed]
         assert (st == 0).all()
         assert np.array_equal(hit[keep].astype(bool), ref)
@@ -138,6 +140,7 @@ def test_scaled_booleans_match_oracle_on_sample(scaled_results):
 def test_scaled_compressed_equals_uncompressed(scaled_results):
     _, out = scaled_results
     assert np.array_equal(out[True][0], out[False][0])
+    assert np.array_equal(out["fp16"][0], out[False][0])
     sc, su = out[True][2], out[False][2]
     assert sc["bv_tests"] > 0 and su["bv_tests"] > 0
     _log(f"scaled stats compressed={sc} uncompressed={su}")
@@ -150,7 +153,7 @@ def proximity_results():
     P = w.raw_poses()
     Pd = torch.from_numpy(P).to(DEV)
     out = {}
-    for compressed in (True, False):
+    for compressed in (True, False, "fp16"):
         ma, mb = models(2, compressed)
         _log(f"proximity distance compressed={compressed}")
         ws = cb.workspace(ma, mb, len(P))
@@ -170,7 +173,7 @@ def test_proximity_distances_match_oracle_on_sample(proximity_results):
     sep = cls == oracle.SEPARATED
     col = cls == oracle.COLLIDING
     assert sep.sum() > 80
-    for compressed in (True, False):
+    for compressed in (True, False, "fp16"):
         d, st, _ = out[compressed]
         assert (st == 0).all()
         got = d[idx].astype(np.float64)
@@ -182,6 +185,7 @@ def test_proximity_distances_match_oracle_on_sample(proximity_results):
 def test_proximity_compressed_equals_uncompressed(proximity_results):
     _, out = proximity_results
     assert np.array_equal(out[True][0].view(np.uint32), out[False][0].view(np.uint32))
+    assert np.array_equal(out["fp16"][0].view(np.uint32), out[False][0].view(np.uint32))
     _log(f"proximity stats compressed={out[True][2]} uncompressed={out[False][2]}")
 
 

@@ -70,3 +70,34 @@ def test_decode_rejects_corrupt_blobs():
     bad[0] = ord("X")
     with pytest.raises(ValueError):
         oracle.blob_decode(bytes(bad))
+
+
+def test_decode_fp16_closed_forms():
+    # a root with two leaf children; every bound a binary16 value whose real
+    # value is known in closed form
+    halves = {0x3C00: 1.0, 0xBC00: -1.0, 0x3555: 0.333251953125, 0x0001: 2.0 ** -24, 0x7BFF: 65504.0,
+              0xC400: -4.0, 0x8400: -(2.0 ** -14), 0x3E00: 1.5, 0x0000: 0.0, 0x4248: 3.140625,
+              0x03FF: 1023 * 2.0 ** -24, 0xD140: -42.0}
+    keys = list(halves)
+    root = [0xC400, 0x7BFF, 0xD140, 0x4248, 0x8400, 0x3E00]          # (lo, hi) per axis
+    c1 = [0xBC00, 0x3C00, 0x0000, 0x3555, 0x0001, 0x03FF]
+    c2 = [0x3555, 0x3E00, 0xBC00, 0x0001, 0x8400, 0x3C00]
+    codes = np.zeros((3, 12), dtype=np.uint8)
+    for i, row in enumerate((root, c1, c2)):
+        codes[i] = np.frombuffer(np.array(row, dtype="<u2").tobytes(), dtype=np.uint8)
+    topo = [topo_word(1, 2), topo_word(0, 1, leaf=True), topo_word(1, 1, leaf=True)]
+    blob = assemble(0, 0x8010, 2, 1, topo, codes, np.zeros((0, 6)), np.zeros((2, 9)), [0, 1], [0, 3],
+                            depth=1)
+    out = oracle.blob_decode(blob)
+    want = np.array([[halves[h] for h in row] for row in (root, c1, c2)], dtype=np.float64)
+    assert np.array_equal(out.astype(np.float64), want)
+    assert set(keys) >= set(root + c1 + c2)
+
+
+def test_decode_fp16_rejects_non_finite_bounds():
+    codes = np.zeros((1, 12), dtype=np.uint8)
+    codes[0, :2] = np.frombuffer(np.array([0x7C00], dtype="<u2").tobytes(), dtype=np.uint8)  # +inf
+    blob = assemble(0, 0x8010, 2, 1, [topo_word(0, 1, leaf=True)], codes, np.zeros((0, 6)),
+                            np.zeros((1, 9)), [0], [0, 1])
+    with pytest.raises(ValueError):
+        oracle.blob_decode(blob)
