@@ -160,6 +160,77 @@ def summarize(r, steps):
     }
 
 
+def run_batched(cb, dev, steps, warmup):
+    """The batched workload: a 20k-triangle link against 64 obstacles of uneven
+    size (1k-200k triangles) in one launch, against the plain kernel run once
+    per obstacle (the fallback), and as a replayed HIP graph."""
+    import torch
+    from synth import configs
+    w = configs.BATCHED
+    kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    progress(f"batched: building {w.n_obstacles} obstacle models")
+    link = cb.Model.build(*w.link_mesh(), **kw).to(dev)
+    obs = [cb.Model.build(*w.obstacle_mesh(i), **kw).to(dev) for i in range(w.n_obstacles)]
+    oset = cb.Obstacles(obs, dev)
+    P, obj = w.raw_poses()
+    n = len(P)
+    Pd, od = torch.from_numpy(P).to(dev), torch.from_numpy(obj).to(dev)
+    ws = cb.workspace(link, link, n, cb.EARLY_EXIT, 0, dev)
+    hit = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def step():
+        cb.cbvh_collide_batch(link.handle, link.dev, oset.handle, Pd, od, n, cb.EARLY_EXIT, hit, st, ws.buf)
+
+    progress(f"batched: {n} poses in {len(w.batches())} batches")
+    wall, dev_ms = time_steps(step, steps, warmup)
+    stats = cb.cbvh_stats(ws.buf)
+    ok = bool((st == 0).all().item())
+    hits = hit.clone()
+    # the plain kernel, one launch per obstacle (poses grouped by obstacle)
+    groups = []
+    for k in range(w.n_obstacles):
+        idx = np.nonzero(obj == k)[0]
+        if len(idx):
+            groups.append((obs[k], torch.from_numpy(P[idx]).to(dev), torch.from_numpy(idx).to(dev),
+                           cb.workspace(link, obs[k], len(idx), cb.EARLY_EXIT, 0, dev),
+                           torch.empty(len(idx), dtype=torch.uint8, device=dev),
+                           torch.empty(len(idx), dtype=torch.uint8, device=dev)))
+    hit_plain = torch.empty(n, dtype=torch.uint8, device=dev)
+
+    def plain_step():
+        for m, Pk, ik, wsk, hk, sk in groups:
+            cb.cbvh_collide(link.handle, link.dev, m.handle, m.dev, Pk, len(Pk), cb.EARLY_EXIT, hk, None, 0, None, sk,
+                            wsk.buf)
+
+    pwall, pdev_ms = time_steps(plain_step, steps, warmup)
+    for m, Pk, ik, wsk, hk, sk in groups:
+        hit_plain[ik] = hk
+    torch.cuda.synchronize()
+    # the batched query captured once and replayed
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        cb.cbvh_collide_batch(link.handle, link.dev, oset.handle, Pd, od, n, cb.EARLY_EXIT, hit, st, ws.buf, stream=s)
+    gwall, gdev_ms = time_steps(g.replay, steps, warmup)
+    graph_equal = bool(torch.equal(hit, hits))
+    progress(f"  batched {np.mean(dev_ms):.3f} ms, plain x{len(groups)} {np.mean(pdev_ms):.3f} ms, "
+             f"graph {np.mean(gdev_ms):.3f} ms")
+    return {
+        "workload": w.name, "poses": n, "batches": len(w.batches()), "obstacles": w.n_obstacles,
+        "obstacle_triangles": int(sum(s_.n_tris for s_ in w.obstacle_specs())),
+        "poses_per_sec": n * steps / wall, "ms_per_call_median": float(np.median(dev_ms)),
+        "ms_per_call_p99": float(np.percentile(dev_ms, 99)), "bv_tests_per_call": stats["bv_tests"],
+        "status_ok": ok, "hits": int(hits.sum().item()),
+        "plain_per_obstacle": {"launches": len(groups), "poses_per_sec": n * steps / pwall,
+                               "ms_per_step_median": float(np.median(pdev_ms)),
+                               "hits_equal": bool(torch.equal(hit_plain, hits))},
+        "graph_replay": {"poses_per_sec": n * steps / gwall, "ms_per_call_median": float(np.median(gdev_ms)),
+                         "hits_equal": graph_equal},
+    }
+
+
 def cpu_baseline(w, threads, budget_s=10.0):
     """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
     host: repeated passes over the workload's poses until about budget_s
@@ -275,6 +346,7 @@ def main():
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
             pr = run_distance(cb, w2, bits, dev, 5, 1)
             out[key] = summarize(pr, 5)
+        out["batched"] = run_batched(cb, dev, 10, 2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, threads=min(16, os.cpu_count() or 1))
     if args.calibrate_copy_mib:

@@ -127,6 +127,7 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 #define CBVH_POSE_STACK_OVERFLOW 1u /* traversal state exhausted and no room to donate it; results invalid */
 #define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
 #define CBVH_POSE_FP64_OVERFLOW 3u  /* workspace buffer of leaf pairs for FP64 re-evaluation full; results invalid */
+#define CBVH_POSE_BAD_OBSTACLE 4u   /* batched queries: the pose's obstacle index is out of range; results invalid */
 
 /* Workspace bytes (device, caller-owned, 256-byte aligned) for a query on
  * models a and b with n poses. */
@@ -166,6 +167,54 @@ cbvh_status cbvh_collide(const cbvh_model *a, const void *a_dev, const cbvh_mode
 cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
                           const float *poses, uint32_t n, uint32_t flags, float *dist, uint8_t *pose_status,
                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- batched queries: many fixed models ("obstacles") in one launch ----
+ *
+ * The batched form of the queries above (section I's use case: test
+ * sampled configurations of one moving body against many obstacles): each
+ * pose names the obstacle it is tested against, and poses for obstacles
+ * of very different sizes share one persistent launch and its work queue.
+ * Answers are identical to running each obstacle's poses through
+ * cbvh_collide / cbvh_distance on their own.
+ *
+ * An obstacle set records the uploaded models' device views in a
+ * caller-owned device table (cbvh_obstacles_device_bytes(n) bytes,
+ * 256-byte aligned).  All models of a set must share BV type and code
+ * width with each other and with the moving model.  The set is host
+ * memory owned by the library; the uploaded models and the table must
+ * stay alive and unchanged while the set is used.  The query functions
+ * copy nothing from the host, so a stream capture of them into a HIP
+ * graph replays correctly. */
+typedef struct cbvh_obstacles cbvh_obstacles;
+
+size_t cbvh_obstacles_device_bytes(uint32_t n);
+
+/* Build a set from n models and their uploaded copies (host arrays of
+ * length n, borrowed for the call) and copy its table to `table`.
+ * Synchronizes `stream`.  CBVH_E_UNSUPPORTED for mixed BV types or code
+ * widths; CBVH_E_CAPACITY if `capacity` is too small. */
+cbvh_status cbvh_obstacles_create(const cbvh_model *const *models, const void *const *devs, uint32_t n, void *table,
+                                  size_t capacity, void *stream, cbvh_obstacles **out);
+
+/* Release a set (NULL is ignored); the table is the caller's. */
+void cbvh_obstacles_free(cbvh_obstacles *set);
+
+/* Collision booleans for poses[i] (moving model a) against obstacle
+ * pose_obstacle[i] of the set (device uint32 [n]; an index >= the set's
+ * size sets CBVH_POSE_BAD_OBSTACLE).  Flags: CBVH_EARLY_EXIT,
+ * CBVH_NO_SPLIT.  The workspace is sized by cbvh_workspace_bytes(a, a, n,
+ * flags, 0); other arguments as for cbvh_collide. */
+cbvh_status cbvh_collide_batch(const cbvh_model *a, const void *a_dev, const cbvh_obstacles *obstacles,
+                               const float *poses, const uint32_t *pose_obstacle, uint32_t n, uint32_t flags,
+                               uint8_t *hit, uint8_t *pose_status, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
+/* Minimum separation distance per pose against its obstacle; as
+ * cbvh_distance otherwise (workspace: cbvh_workspace_bytes(a, a, n, 0, 0)). */
+cbvh_status cbvh_distance_batch(const cbvh_model *a, const void *a_dev, const cbvh_obstacles *obstacles,
+                                const float *poses, const uint32_t *pose_obstacle, uint32_t n, uint32_t flags,
+                                float *dist, uint8_t *pose_status, void *workspace, size_t workspace_bytes,
+                                void *stream);
 
 /* Decode every node's bounds on the device: out = device float32
  * [n_nodes][2*slabs] as (lo, hi) per slab.  Parity tool for the decoder. */

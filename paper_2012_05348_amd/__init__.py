@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libcbvh.so")
 AABB, DOP18 = 0, 1
 BITS_FP16 = 0x8010  # half-precision absolute descriptors (CBVH_BITS_FP16)
 EARLY_EXIT, PAIRS, NO_SPLIT = 0x1, 0x2, 0x4
-POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW = 0, 1, 2, 3
+POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW, POSE_BAD_OBSTACLE = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_CAPACITY", 5: "E_UNSUPPORTED", 6: "E_FORMAT"}
 
 
@@ -77,6 +77,11 @@ def lib():
             "cbvh_workspace_bytes": (sz, [P, P, u32, u32, u32]),
             "cbvh_collide": (st, [P, P, P, P, P, u32, u32, P, P, u32, P, P, P, sz, P]),
             "cbvh_distance": (st, [P, P, P, P, P, u32, u32, P, P, P, sz, P]),
+            "cbvh_obstacles_device_bytes": (sz, [u32]),
+            "cbvh_obstacles_create": (st, [C.POINTER(P), C.POINTER(P), u32, P, sz, P, C.POINTER(P)]),
+            "cbvh_obstacles_free": (None, [P]),
+            "cbvh_collide_batch": (st, [P, P, P, P, P, u32, u32, P, P, P, sz, P]),
+            "cbvh_distance_batch": (st, [P, P, P, P, P, u32, u32, P, P, P, sz, P]),
             "cbvh_decode_all": (st, [P, P, P, P]),
             "cbvh_stats": (st, [P, sz, C.POINTER(Stats), P]),
             "cbvh_set_stack_limits": (st, [u32, u32]),
@@ -172,6 +177,39 @@ def cbvh_collide(a, a_dev, b, b_dev, poses, n, flags, hit, pairs, pair_capacity,
 def cbvh_distance(a, a_dev, b, b_dev, poses, n, flags, dist, pose_status, workspace, stream=None):
     _check(lib().cbvh_distance(a, _ptr(a_dev), b, _ptr(b_dev), _ptr(poses), n, flags, _ptr(dist), _ptr(pose_status),
                                _ptr(workspace), 0 if workspace is None else workspace.numel(), _stream(stream)))
+
+
+def cbvh_obstacles_device_bytes(n) -> int:
+    return int(lib().cbvh_obstacles_device_bytes(n))
+
+
+def cbvh_obstacles_create(handles, devs, table, stream=None):
+    n = len(handles)
+    hs = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    ds = (C.c_void_p * n)(*[d.data_ptr() for d in devs])
+    out = C.c_void_p()
+    _check(lib().cbvh_obstacles_create(C.cast(hs, C.POINTER(C.c_void_p)), C.cast(ds, C.POINTER(C.c_void_p)), n,
+                                       _ptr(table), table.numel() * table.element_size(), _stream(stream),
+                                       C.byref(out)))
+    return out
+
+
+def cbvh_obstacles_free(h):
+    if h:
+        lib().cbvh_obstacles_free(h)
+
+
+def cbvh_collide_batch(a, a_dev, obstacles, poses, pose_obstacle, n, flags, hit, pose_status, workspace, stream=None):
+    _check(lib().cbvh_collide_batch(a, _ptr(a_dev), obstacles, _ptr(poses), _ptr(pose_obstacle), n, flags, _ptr(hit),
+                                    _ptr(pose_status), _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                    _stream(stream)))
+
+
+def cbvh_distance_batch(a, a_dev, obstacles, poses, pose_obstacle, n, flags, dist, pose_status, workspace,
+                        stream=None):
+    _check(lib().cbvh_distance_batch(a, _ptr(a_dev), obstacles, _ptr(poses), _ptr(pose_obstacle), n, flags,
+                                     _ptr(dist), _ptr(pose_status), _ptr(workspace),
+                                     0 if workspace is None else workspace.numel(), _stream(stream)))
 
 
 def cbvh_decode_all(h, dev, out, stream=None):
@@ -289,4 +327,53 @@ def distance(a: Model, b: Model, poses, flags=0, ws: Workspace | None = None, ou
     else:
         dist, status = out
     cbvh_distance(a.handle, a.dev, b.handle, b.dev, poses, n, flags, dist, status, ws.buf)
+    return dist, status
+
+
+class Obstacles:
+    """A set of uploaded fixed models for batched queries (keeps the models alive)."""
+
+    def __init__(self, models, device="cuda"):
+        self.models = list(models)
+        self.table = _aligned_empty(max(256, cbvh_obstacles_device_bytes(len(self.models))), device)
+        self._h = cbvh_obstacles_create([m.handle for m in self.models], [m.dev for m in self.models], self.table)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.cbvh_obstacles_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return len(self.models)
+
+
+def collide_batch(a: Model, obstacles: Obstacles, poses, pose_obstacle, flags=EARLY_EXIT, ws: Workspace | None = None,
+                  out=None):
+    """Batched collision booleans: pose i (float32 [n, 3, 4]) against obstacle pose_obstacle[i] (int32/uint32 [n])."""
+    import torch
+    n = int(poses.shape[0])
+    dev = poses.device
+    if ws is None:
+        ws = workspace(a, a, n, flags, 0, dev)
+    hit, status = out if out is not None else (torch.empty(n, dtype=torch.uint8, device=dev),
+                                               torch.empty(n, dtype=torch.uint8, device=dev))
+    cbvh_collide_batch(a.handle, a.dev, obstacles.handle, poses, pose_obstacle, n, flags, hit, status, ws.buf)
+    return hit, status
+
+
+def distance_batch(a: Model, obstacles: Obstacles, poses, pose_obstacle, flags=0, ws: Workspace | None = None,
+                   out=None):
+    """Batched minimum distances: pose i against obstacle pose_obstacle[i]."""
+    import torch
+    n = int(poses.shape[0])
+    dev = poses.device
+    if ws is None:
+        ws = workspace(a, a, n, 0, 0, dev)
+    dist, status = out if out is not None else (torch.empty(n, dtype=torch.float32, device=dev),
+                                                torch.empty(n, dtype=torch.uint8, device=dev))
+    cbvh_distance_batch(a.handle, a.dev, obstacles.handle, poses, pose_obstacle, n, flags, dist, status, ws.buf)
     return dist, status

@@ -6,11 +6,20 @@
 #include <atomic>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/cbvh.h"
 #include "format.h"
 #include "kernels.h"
 #include "model.h"
+
+// A set of fixed models for batched queries: their device views, copied to
+// a caller-owned device table.
+struct cbvh_obstacles {
+    uint32_t n, bv, bits;
+    const cbvh::DevModel *dev_table;
+    std::vector<cbvh::DevModel> host;
+};
 
 namespace {
 
@@ -121,10 +130,21 @@ cbvh_status check_pair(const cbvh_model *a, const void *a_dev, const cbvh_model 
 cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
                       const float *poses, uint32_t n, int mode, uint32_t flags, uint8_t *hit, float *dist,
                       uint32_t *pairs, uint32_t pair_cap, uint32_t *pair_offsets, uint8_t *status, void *ws,
-                      size_t ws_bytes, void *stream)
+                      size_t ws_bytes, void *stream, const cbvh_obstacles *obs = nullptr,
+                      const uint32_t *pose_obj = nullptr)
 {
-    cbvh_status st = check_pair(a, a_dev, b, b_dev);
-    if (st != CBVH_OK) return st;
+    cbvh_status st;
+    if (obs) {
+        if (!a || !a_dev) return fail(CBVH_E_INVALID, "model is NULL");
+        if (!aligned(a_dev, 256)) return fail(CBVH_E_INVALID, "device model not 256-byte aligned");
+        if (a->hdr.bv != obs->bv) return fail(CBVH_E_UNSUPPORTED, "models have different BV types");
+        if (a->hdr.bits != obs->bits) return fail(CBVH_E_UNSUPPORTED, "models have different code widths");
+        if (n && !pose_obj) return fail(CBVH_E_INVALID, "pose_obstacle is NULL");
+        if (!aligned(pose_obj, 4)) return fail(CBVH_E_INVALID, "pose_obstacle not 4-byte aligned");
+    } else {
+        st = check_pair(a, a_dev, b, b_dev);
+        if (st != CBVH_OK) return st;
+    }
     if (n == 0) return CBVH_OK;
     if (!poses || !status) return fail(CBVH_E_INVALID, "poses or pose_status is NULL");
     if (mode == cbvh::MODE_DIST ? !dist : !hit) return fail(CBVH_E_INVALID, "output array is NULL");
@@ -143,7 +163,14 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     cbvh::QueryArgs q;
     memset(&q, 0, sizeof q);
     q.A = dev_view(a, a_dev);
-    q.B = dev_view(b, b_dev);
+    if (obs) {
+        q.B = obs->host[0];
+        q.Btab = obs->dev_table;
+        q.pose_obj = pose_obj;
+        q.n_obj = obs->n;
+    } else {
+        q.B = dev_view(b, b_dev);
+    }
     q.poses = poses;
     q.n_poses = n;
     q.mode = mode;
@@ -311,6 +338,74 @@ cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_mod
     if (flags & ~CBVH_NO_SPLIT) return fail(CBVH_E_INVALID, "unknown flag");
     return run_query(a, a_dev, b, b_dev, poses, n, cbvh::MODE_DIST, flags, nullptr, dist, nullptr, 0, nullptr,
                      pose_status, workspace, workspace_bytes, stream);
+}
+
+size_t cbvh_obstacles_device_bytes(uint32_t n) { return (size_t)align_up((uint64_t)n * sizeof(cbvh::DevModel), 256); }
+
+cbvh_status cbvh_obstacles_create(const cbvh_model *const *models, const void *const *devs, uint32_t n, void *table,
+                                  size_t capacity, void *stream, cbvh_obstacles **out)
+{
+    if (!out) return fail(CBVH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!models || !devs || !table || n == 0) return fail(CBVH_E_INVALID, "NULL argument or no models");
+    if (n > (1u << 24)) return fail(CBVH_E_INVALID, "too many models");
+    if (!aligned(table, 256)) return fail(CBVH_E_INVALID, "table not 256-byte aligned");
+    if (capacity < cbvh_obstacles_device_bytes(n)) return fail(CBVH_E_CAPACITY, "table too small");
+    try {
+        cbvh_obstacles *o = new cbvh_obstacles();
+        o->n = n;
+        o->host.reserve(n);
+        for (uint32_t i = 0; i < n; i++) {
+            if (!models[i] || !devs[i] || !aligned(devs[i], 256)) {
+                delete o;
+                return fail(CBVH_E_INVALID, "model " + std::to_string(i) + " NULL or device copy not 256-byte aligned");
+            }
+            if (i == 0) {
+                o->bv = models[0]->hdr.bv;
+                o->bits = models[0]->hdr.bits;
+            } else if (models[i]->hdr.bv != o->bv || models[i]->hdr.bits != o->bits) {
+                delete o;
+                return fail(CBVH_E_UNSUPPORTED, "models of one set must share BV type and code width");
+            }
+            o->host.push_back(dev_view(models[i], devs[i]));
+        }
+        o->dev_table = (const cbvh::DevModel *)table;
+        hipError_t e = hipMemcpyAsync(table, o->host.data(), sizeof(cbvh::DevModel) * (size_t)n, hipMemcpyHostToDevice,
+                                      (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) {
+            delete o;
+            return fail_hip(e, "model table copy");
+        }
+        *out = o;
+        return CBVH_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(CBVH_E_NOMEM, "out of host memory");
+    }
+}
+
+void cbvh_obstacles_free(cbvh_obstacles *o) { delete o; }
+
+cbvh_status cbvh_collide_batch(const cbvh_model *a, const void *a_dev, const cbvh_obstacles *obstacles,
+                               const float *poses, const uint32_t *pose_obstacle, uint32_t n, uint32_t flags,
+                               uint8_t *hit, uint8_t *pose_status, void *workspace, size_t workspace_bytes,
+                               void *stream)
+{
+    if (!obstacles) return fail(CBVH_E_INVALID, "obstacles is NULL");
+    if (flags & ~(CBVH_EARLY_EXIT | CBVH_NO_SPLIT)) return fail(CBVH_E_INVALID, "unknown or unsupported flag");
+    return run_query(a, a_dev, nullptr, nullptr, poses, n, cbvh::MODE_BOOL, flags, hit, nullptr, nullptr, 0, nullptr,
+                     pose_status, workspace, workspace_bytes, stream, obstacles, pose_obstacle);
+}
+
+cbvh_status cbvh_distance_batch(const cbvh_model *a, const void *a_dev, const cbvh_obstacles *obstacles,
+                                const float *poses, const uint32_t *pose_obstacle, uint32_t n, uint32_t flags,
+                                float *dist, uint8_t *pose_status, void *workspace, size_t workspace_bytes,
+                                void *stream)
+{
+    if (!obstacles) return fail(CBVH_E_INVALID, "obstacles is NULL");
+    if (flags & ~CBVH_NO_SPLIT) return fail(CBVH_E_INVALID, "unknown flag");
+    return run_query(a, a_dev, nullptr, nullptr, poses, n, cbvh::MODE_DIST, flags, nullptr, dist, nullptr, 0, nullptr,
+                     pose_status, workspace, workspace_bytes, stream, obstacles, pose_obstacle);
 }
 
 cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, void *stream)

@@ -87,6 +87,11 @@ struct Workspace {
 
 struct QueryArgs {
     DevModel A, B;
+    // batched queries over several fixed models: pose i is tested against
+    // Btab[pose_obj[i]] (pose_obj == nullptr: every pose against B)
+    const DevModel *Btab;
+    const uint32_t *pose_obj;
+    uint32_t n_obj;
     const float *poses;
     uint32_t n_poses;
     int mode;

@@ -403,11 +403,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass       // dwords per item
     constexpr uint32_t IPI = (uint32_t)WAVE / IW;   // items written per wave instruction
     const DevModel &MA = q.A;
-    const DevModel &MB = q.B;
+    DevModel MB = q.B;  // the fixed model of the current unit (per pose in batched queries)
     WsHeader *hdr = q.ws.hdr;
     Counters cnt;
-    const uint32_t lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
-    const uint32_t code_bytes_A = 4 + MA.stride, code_bytes_B = 4 + MB.stride;
+    uint32_t lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
+    const uint32_t code_bytes_A = 4 + MA.stride;
+    uint32_t code_bytes_B = 4 + MB.stride;
     const bool can_donate = !q.no_split;
     unsigned long long t_first = 0, t_drain = ~0ull;
 
@@ -545,6 +546,20 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             }
         }
         if (pose != cur_pose) {
+            if (q.pose_obj) {
+                // batched query: this pose's fixed model
+                const uint32_t obj = uni(q.pose_obj[pose]);
+                if (obj >= q.n_obj) {
+                    if (lane == 0) {
+                        q.status[pose] = 4;  // CBVH_POSE_BAD_OBSTACLE
+                        if (can_donate) rmw_add(&hdr->pending, 0xFFFFFFFFu);
+                    }
+                    continue;
+                }
+                MB = q.Btab[obj];
+                lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
+                code_bytes_B = 4 + MB.stride;
+            }
             cur_pose = pose;
 #pragma unroll
             for (int i = 0; i < 3; i++) {
@@ -1156,8 +1171,9 @@ __global__ __launch_bounds__(256) void fix_kernel(QueryArgs q)
         const uint32_t pose = f.x;
         if (MODE == MODE_BOOL && q.hit[pose]) continue;
         const float *pp = q.poses + 12 * (size_t)pose;
+        const DevModel &B = q.pose_obj ? q.Btab[q.pose_obj[pose]] : q.B;  // validated by the traversal
         if (MODE == MODE_DIST) {
-            const float e = dist_err_abs(pp, q.A.max_abs, q.B.max_abs);
+            const float e = dist_err_abs(pp, q.A.max_abs, B.max_abs);
             if (__uint_as_float(f.w) > add_up(__uint_as_float(q.ws.best32[pose]), 2.0f * e)) continue;
         }
         Pose P;
@@ -1169,7 +1185,7 @@ __global__ __launch_bounds__(256) void fix_kernel(QueryArgs q)
         }
         V3<float> a0[3], b0[3];
         load_tri(q.A.tris, f.y, a0);
-        load_tri(q.B.tris, f.z, b0);
+        load_tri(B.tris, f.z, b0);
         V3<double> a64[3], b64[3];
 #pragma unroll
         for (int v = 0; v < 3; v++) {
@@ -1183,7 +1199,7 @@ __global__ __launch_bounds__(256) void fix_kernel(QueryArgs q)
             if (inter) {
                 q.hit[pose] = 1;
                 const uint32_t idx = atomicAdd(&q.ws.hdr->pair_count, 1u);
-                if (idx < q.pair_cap) q.ws.pair_raw[idx] = make_uint4(pose, q.A.perm[f.y], q.B.perm[f.z], 0u);
+                if (idx < q.pair_cap) q.ws.pair_raw[idx] = make_uint4(pose, q.A.perm[f.y], B.perm[f.z], 0u);
                 else if (q.status[pose] == 0) q.status[pose] = 2;  // CBVH_POSE_PAIR_OVERFLOW
             }
         } else {

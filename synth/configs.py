@@ -89,3 +89,83 @@ WORKLOADS = {
     2: Workload(2, "proximity: icosphere 50k vs torus 50k, AABB BF4 leaf1, 8-bit, distances",
                 ICO50, TORUS50K, "aabb", 4, 1, 8, 4096, "distance", ("shell", 2.0, 4.0)),
 }
+
+
+# ---------------------------------------------------------------------------
+# Batched workload: one moving link against many obstacles of uneven size
+# ---------------------------------------------------------------------------
+TORUS20K = MeshSpec("torus", (200, 50), 0.02)  # 20,000 triangles
+
+
+@dataclass(frozen=True)
+class BatchedWorkload:
+    """A robot link (20k-triangle torus, moving) queried against ``n_obstacles``
+    obstacle meshes whose triangle counts are log-uniform in [tri_min, tri_max]
+    (noisy icospheres or tori, each with probability 1/2).  Pose batches cycle
+    through the obstacles; each batch has a log-uniform size in
+    [batch_min, batch_max]; batches are drawn until ``min_poses`` poses exist.
+    Seeds: stream 0 the link, 3 obstacle kinds and sizes, 5 batch sizes,
+    2 poses, 100 + i obstacle i."""
+    index: int = 3
+    n_obstacles: int = 64
+    tri_min: int = 1000
+    tri_max: int = 200000
+    batch_min: int = 1
+    batch_max: int = 1024
+    min_poses: int = 30000
+    link: MeshSpec = TORUS20K
+    bv: str = "dop18"
+    branching: int = 8
+    leaf_size: int = 4
+    bits: int = 16
+    query: str = "bool"
+    translation: tuple = ("box", 2.5)
+    margin_rel: float = 1e-4
+
+    @property
+    def name(self):
+        return (f"batched: torus 20k link vs {self.n_obstacles} obstacles ({self.tri_min}-{self.tri_max} tri), "
+                f"18-DOP BF{self.branching} leaf {self.leaf_size}, {self.bits}-bit, booleans")
+
+    def obstacle_specs(self):
+        rng = rng_for(self.index, 3)
+        kinds = rng.random(self.n_obstacles) < 0.5
+        sizes = np.exp(rng.uniform(np.log(self.tri_min), np.log(self.tri_max), self.n_obstacles))
+        specs = []
+        for is_ico, n in zip(kinds, sizes):
+            if is_ico:
+                specs.append(MeshSpec("icosphere", (max(1, int(round((n / 20.0) ** 0.5))),), 0.1))
+            else:
+                specs.append(MeshSpec("torus", meshes.torus_grid_for(int(n)), 0.02))
+        return specs
+
+    def obstacle_mesh(self, i: int):
+        return self.obstacle_specs()[i].make(rng_for(self.index, 100 + i))
+
+    def link_mesh(self):
+        return self.link.make(rng_for(self.index, 0))
+
+    def batches(self):
+        """[(obstacle, count)] in launch order."""
+        rng = rng_for(self.index, 5)
+        out, total, i = [], 0, 0
+        while total < self.min_poses:
+            c = int(np.floor(np.exp(rng.uniform(np.log(self.batch_min), np.log(self.batch_max + 1)))))
+            c = min(max(c, self.batch_min), self.batch_max)
+            out.append((i % self.n_obstacles, c))
+            total += c
+            i += 1
+        return out
+
+    def raw_poses(self):
+        """(poses float32 [n, 3, 4], obstacle index uint32 [n]), batches contiguous."""
+        b = self.batches()
+        n = sum(c for _, c in b)
+        rng = rng_for(self.index, 2)
+        R = poses.uniform_rotations(n, rng)
+        t = poses.box_translations(n, self.translation[1], rng)
+        obj = np.concatenate([np.full(c, o, dtype=np.uint32) for o, c in b])
+        return poses.compose(R, t), obj
+
+
+BATCHED = BatchedWorkload()
