@@ -169,8 +169,10 @@ def run_batched(cb, dev, steps, warmup):
     w = configs.BATCHED
     kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
     progress(f"batched: building {w.n_obstacles} obstacle models")
-    link = cb.Model.build(*w.link_mesh(), **kw).to(dev)
-    obs = [cb.Model.build(*w.obstacle_mesh(i), **kw).to(dev) for i in range(w.n_obstacles)]
+    link_mesh = w.link_mesh()
+    obs_meshes = [w.obstacle_mesh(i) for i in range(w.n_obstacles)]
+    link = cb.Model.build(*link_mesh, **kw).to(dev)
+    obs = [cb.Model.build(*m, **kw).to(dev) for m in obs_meshes]
     oset = cb.Obstacles(obs, dev)
     P, obj = w.raw_poses()
     n = len(P)
@@ -217,7 +219,13 @@ def run_batched(cb, dev, steps, warmup):
     graph_equal = bool(torch.equal(hit, hits))
     progress(f"  batched {np.mean(dev_ms):.3f} ms, plain x{len(groups)} {np.mean(pdev_ms):.3f} ms, "
              f"graph {np.mean(gdev_ms):.3f} ms")
+    # autotuner over branching factor and waves per CU (answers must not change)
+    from paper_2012_05348_amd import autotune
+    progress("batched: autotune (branching 4/8, waves per CU as many as fit / 8)")
+    tuned = autotune.tune(link_mesh, obs_meshes, P, obj, bits=w.bits, leaf_size=w.leaf_size, branchings=(4, 8),
+                          treelet_bytes=(8192,), waves_per_cu=(0, 8), steps=5, warmup=2, device=dev)
     return {
+        "autotune": tuned,
         "workload": w.name, "poses": n, "batches": len(w.batches()), "obstacles": w.n_obstacles,
         "obstacle_triangles": int(sum(s_.n_tris for s_ in w.obstacle_specs())),
         "poses_per_sec": n * steps / wall, "ms_per_call_median": float(np.median(dev_ms)),

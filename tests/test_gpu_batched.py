@@ -151,3 +151,16 @@ def test_batched_query_replays_from_a_hip_graph(setup):
         cb.collide_batch(link, oset, Pd, od, ws=ws, out=(hit, st))  # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(hit, eager)
+
+
+def test_autotuner_keeps_answers_and_picks_a_candidate(setup):
+    from paper_2012_05348_amd import autotune
+    w, link_mesh, obs_meshes, link, obs, P, obj = setup
+    n = 512
+    res = autotune.tune(link_mesh, obs_meshes, P[:n], obj[:n], bits=w.bits, leaf_size=w.leaf_size,
+                        branchings=(4, 8), treelet_bytes=(8192,), waves_per_cu=(0, 8), steps=2, warmup=1,
+                        device=DEV)
+    assert len(res["results"]) == 4 and res["all_answers_equal"]
+    best = res["best"]
+    assert best is not None and best["ms"] == min(r["ms"] for r in res["results"])
+    assert "CBVH_WAVES_PER_CU" not in os.environ
