@@ -239,6 +239,39 @@ def run_batched(cb, dev, steps, warmup):
     }
 
 
+def run_serving(cb, dev, n_requests=1500):
+    """The serving workload: 32 resident obstacles (1k-200k triangles), requests
+    of 1-4096 random-walk poses against a uniform obstacle, 70 % collision and
+    30 % distance.  First the saturation rate (every request available at
+    once), then Poisson arrivals at 50/80/95 % of it with p50/p99 latency."""
+    from paper_2012_05348_amd import serve
+    from synth import configs
+    w = configs.SERVING
+    kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    progress(f"serving: building {w.n_obstacles} resident obstacle models")
+    link = cb.Model.build(*w.link_mesh(), **kw).to(dev)
+    oset = cb.Obstacles([cb.Model.build(*w.obstacle_mesh(i), **kw).to(dev) for i in range(w.n_obstacles)], dev)
+    srv = serve.Server(link, oset, dev)
+    rng = configs.rng_for(4, 2)
+    warm = serve.make_requests(200, np.inf, w.n_obstacles, rng)
+    srv.run(warm, realtime=False)
+    sat_req = serve.make_requests(n_requests, np.inf, w.n_obstacles, rng)
+    sat = srv.run(sat_req, realtime=False)
+    rate = sat["requests_per_sec"]
+    out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests,
+           "saturation": {k: sat[k] for k in ("poses_per_sec", "requests_per_sec", "launches", "p50_ms", "p99_ms")}}
+    progress(f"serving: saturation {sat['poses_per_sec']:.3g} poses/s, {rate:.0f} requests/s")
+    for frac in (0.5, 0.8, 0.95):
+        req = serve.make_requests(n_requests, frac * rate, w.n_obstacles, rng)
+        r = srv.run(req, realtime=True)
+        ok = bool((r["status"] == 0).all())
+        out[f"load_{int(frac * 100)}"] = {"offered_requests_per_sec": frac * rate, "poses_per_sec": r["poses_per_sec"],
+                                          "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "launches": r["launches"],
+                                          "status_ok": ok}
+        progress(f"  load {frac:.0%}: p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms")
+    return out
+
+
 def cpu_baseline(w, threads, budget_s=10.0):
     """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
     host: repeated passes over the workload's poses until about budget_s
@@ -355,6 +388,7 @@ def main():
             pr = run_distance(cb, w2, bits, dev, 5, 1)
             out[key] = summarize(pr, 5)
         out["batched"] = run_batched(cb, dev, 10, 2)
+        out["serving"] = run_serving(cb, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, threads=min(16, os.cpu_count() or 1))
     if args.calibrate_copy_mib:

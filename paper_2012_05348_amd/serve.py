@@ -1,0 +1,215 @@
+"""Serving loop with continuous batching for collision and distance requests
+against resident obstacle models (the motion-planning use case of the
+paper's introduction: configurations sampled by a planner are tested
+against a fixed set of obstacles as they arrive).
+
+A request is a batch of poses of the moving model against one obstacle,
+either a collision query (booleans) or a distance query.  The loop keeps a
+few launch slots per query kind, each with its own HIP stream, device
+buffers and workspace, sized so that all slots fit a device-memory budget.
+Whenever a slot is free it admits every request that has arrived and fits
+(one batched launch covers requests for different obstacles), and
+completions are polled without blocking, so requests that arrive while
+others run are admitted as slots and memory free up, and work of different
+requests overlaps on the device.  Results are per pose and do not depend
+on what else shares the launch.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (EARLY_EXIT, Model, Obstacles, cbvh_collide_batch, cbvh_distance_batch, cbvh_workspace_bytes,
+               _aligned_empty)
+
+COLLIDE, DISTANCE = 0, 1
+
+
+@dataclass
+class Requests:
+    """Requests in arrival order; request r owns poses[first[r] : first[r] + count[r]]."""
+    arrival: np.ndarray   # float64 [R], seconds after the start
+    kind: np.ndarray      # uint8 [R], COLLIDE or DISTANCE
+    obstacle: np.ndarray  # uint32 [R]
+    first: np.ndarray     # int64 [R]
+    count: np.ndarray     # int64 [R]
+    poses: np.ndarray     # float32 [N, 3, 4]
+
+    def __len__(self):
+        return len(self.arrival)
+
+
+def _qmul(a, b):
+    aw, ax, ay, az = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    bw, bx, by, bz = b[..., 0], b[..., 1], b[..., 2], b[..., 3]
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw], axis=-1)
+
+
+def _unit(rng, n):
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def make_requests(n_requests, rate, n_obstacles, rng, batch_min=1, batch_max=4096, collide_frac=0.7,
+                  rot_step=0.05, trans_step=0.02, box=2.5):
+    """Poisson arrivals at `rate` requests/s (rate = inf: all at time 0), batch
+    sizes log-uniform in [batch_min, batch_max], obstacles uniform, a
+    collide/distance mix, and each request's poses a random walk: a uniform
+    start (rotation uniform, translation uniform in [-box, box]^3), then steps
+    rotating by an angle in [0, rot_step] about a uniform axis and moving by
+    a length in [0, trans_step] along a uniform direction."""
+    R = n_requests
+    gaps = np.zeros(R) if not np.isfinite(rate) else rng.exponential(1.0 / rate, R)
+    arrival = np.cumsum(gaps) - (gaps[0] if R else 0.0)
+    kind = np.where(rng.random(R) < collide_frac, COLLIDE, DISTANCE).astype(np.uint8)
+    obstacle = rng.integers(0, n_obstacles, R).astype(np.uint32)
+    count = np.floor(np.exp(rng.uniform(np.log(batch_min), np.log(batch_max + 1), R))).astype(np.int64)
+    count = np.clip(count, batch_min, batch_max)
+    first = np.concatenate([[0], np.cumsum(count)[:-1]]).astype(np.int64)
+    N = int(count.sum())
+    # start poses: Shoemake uniform quaternions, uniform translations
+    u1, u2, u3 = rng.random(R), rng.random(R), rng.random(R)
+    q = np.stack([np.sqrt(1 - u1) * np.sin(2 * np.pi * u2), np.sqrt(1 - u1) * np.cos(2 * np.pi * u2),
+                  np.sqrt(u1) * np.sin(2 * np.pi * u3), np.sqrt(u1) * np.cos(2 * np.pi * u3)], axis=1)
+    t = rng.uniform(-box, box, size=(R, 3))
+    Q = np.empty((N, 4))
+    T = np.empty((N, 3))
+    for s in range(int(count.max()) if R else 0):
+        act = np.nonzero(count > s)[0]
+        if s > 0:
+            ang = rng.uniform(0.0, rot_step, len(act))
+            ax = _unit(rng, len(act))
+            dq = np.concatenate([np.cos(ang / 2)[:, None], np.sin(ang / 2)[:, None] * ax], axis=1)
+            q[act] = _qmul(dq, q[act])
+            q[act] /= np.linalg.norm(q[act], axis=1, keepdims=True)
+            t[act] += _unit(rng, len(act)) * rng.uniform(0.0, trans_step, len(act))[:, None]
+        Q[first[act] + s] = q[act]
+        T[first[act] + s] = t[act]
+    w, x, y, z = Q[:, 0], Q[:, 1], Q[:, 2], Q[:, 3]
+    M = np.empty((N, 3, 4))
+    M[:, 0, 0], M[:, 0, 1], M[:, 0, 2] = 1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)
+    M[:, 1, 0], M[:, 1, 1], M[:, 1, 2] = 2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)
+    M[:, 2, 0], M[:, 2, 1], M[:, 2, 2] = 2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)
+    M[:, :, 3] = T
+    return Requests(arrival, kind, obstacle, first, count, M.astype(np.float32))
+
+
+class _Slot:
+    def __init__(self, link, kind, max_poses, device):
+        import torch
+        self.kind = kind
+        self.stream = torch.cuda.Stream(device=device)
+        self.P = torch.empty((max_poses, 3, 4), dtype=torch.float32, device=device)
+        self.obj = torch.empty(max_poses, dtype=torch.int32, device=device)
+        self.out = torch.empty(max_poses, dtype=torch.uint8 if kind == COLLIDE else torch.float32, device=device)
+        self.status = torch.empty(max_poses, dtype=torch.uint8, device=device)
+        self.ws = _aligned_empty(cbvh_workspace_bytes(link.handle, link.handle, max_poses,
+                                                      EARLY_EXIT if kind == COLLIDE else 0, 0), device)
+        self.event = torch.cuda.Event()
+        self.busy = None  # (request range lo, hi, pose range lo, hi) while a launch is in flight
+
+
+class Server:
+    """Continuous-batching request loop over a resident obstacle set."""
+
+    def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
+                 memory_budget=2 << 30, max_poses=None):
+        self.link, self.obstacles, self.device = link, obstacles, device
+        # the largest launch that lets every slot's workspace fit the budget
+        if max_poses is None:
+            lo, hi = 4096, 1 << 22
+            while lo < hi:
+                mid = (lo + hi + 1) // 2
+                need = slots_per_kind * sum(cbvh_workspace_bytes(link.handle, link.handle, mid, f, 0)
+                                            for f in (EARLY_EXIT, 0))
+                if need <= memory_budget:
+                    lo = mid
+                else:
+                    hi = mid - 1
+            max_poses = lo
+        self.max_poses = max_poses
+        self.slots = [_Slot(link, k, max_poses, device) for k in (COLLIDE, DISTANCE) for _ in range(slots_per_kind)]
+
+    def run(self, req: Requests, realtime=True):
+        """Serve every request; returns per-request latencies (s), per-pose results
+        (booleans and distances in request pose order) and throughput."""
+        import torch
+        R, N = len(req), len(req.poses)
+        # per kind: its requests in arrival order and their poses, contiguous
+        kinds = {}
+        for k in (COLLIDE, DISTANCE):
+            rs = np.nonzero(req.kind == k)[0]
+            pidx = np.concatenate([np.arange(req.first[r], req.first[r] + req.count[r]) for r in rs]) if len(rs) \
+                else np.zeros(0, dtype=np.int64)
+            pstart = np.concatenate([[0], np.cumsum(req.count[rs])]).astype(np.int64)
+            P = torch.from_numpy(np.ascontiguousarray(req.poses[pidx])).pin_memory()
+            obj = torch.from_numpy(np.repeat(req.obstacle[rs], req.count[rs]).astype(np.int32)).pin_memory()
+            out = torch.empty(len(pidx), dtype=torch.uint8 if k == COLLIDE else torch.float32).pin_memory()
+            status = torch.empty(len(pidx), dtype=torch.uint8).pin_memory()
+            kinds[k] = dict(rs=rs, pidx=pidx, pstart=pstart, P=P, obj=obj, out=out, status=status, next=0)
+        done_at = np.full(R, np.nan)
+        n_launch = 0
+        max_batch = 0
+        t0 = time.perf_counter()
+        remaining = R
+        while remaining:
+            now = time.perf_counter() - t0
+            progressed = False
+            for s in self.slots:
+                if s.busy is not None and s.event.query():
+                    lo, hi, _, _ = s.busy
+                    done_at[kinds[s.kind]["rs"][lo:hi]] = time.perf_counter() - t0
+                    remaining -= hi - lo
+                    s.busy = None
+                    progressed = True
+                if s.busy is not None:
+                    continue
+                K = kinds[s.kind]
+                lo = K["next"]
+                if lo >= len(K["rs"]):
+                    continue
+                # admit every arrived request that fits this slot
+                arrived_t = now if realtime else np.inf
+                hi = lo
+                while hi < len(K["rs"]) and req.arrival[K["rs"][hi]] <= arrived_t and \
+                        K["pstart"][hi + 1] - K["pstart"][lo] <= self.max_poses:
+                    hi += 1
+                if hi == lo:
+                    continue
+                p0, p1 = int(K["pstart"][lo]), int(K["pstart"][hi])
+                n = p1 - p0
+                with torch.cuda.stream(s.stream):
+                    s.P[:n].copy_(K["P"][p0:p1], non_blocking=True)
+                    s.obj[:n].copy_(K["obj"][p0:p1], non_blocking=True)
+                    if s.kind == COLLIDE:
+                        cbvh_collide_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n,
+                                           EARLY_EXIT, s.out, s.status, s.ws, stream=s.stream)
+                    else:
+                        cbvh_distance_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n, 0,
+                                            s.out, s.status, s.ws, stream=s.stream)
+                    K["out"][p0:p1].copy_(s.out[:n], non_blocking=True)
+                    K["status"][p0:p1].copy_(s.status[:n], non_blocking=True)
+                    s.event.record(s.stream)
+                s.busy = (lo, hi, p0, p1)
+                K["next"] = hi
+                n_launch += 1
+                max_batch = max(max_batch, n)
+                progressed = True
+            if not progressed:
+                time.sleep(20e-6)
+        makespan = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        hit = np.zeros(N, dtype=np.uint8)
+        dist = np.full(N, np.nan, dtype=np.float32)
+        status = np.zeros(N, dtype=np.uint8)
+        for k, K in kinds.items():
+            (hit if k == COLLIDE else dist)[K["pidx"]] = K["out"].numpy()
+            status[K["pidx"]] = K["status"].numpy()
+        lat = done_at - req.arrival
+        return {"latency_s": lat, "hit": hit, "dist": dist, "status": status, "makespan_s": makespan,
+                "poses_per_sec": N / makespan, "requests_per_sec": R / makespan, "launches": n_launch,
+                "largest_launch": max_batch, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3)}

@@ -169,3 +169,8 @@ class BatchedWorkload:
 
 
 BATCHED = BatchedWorkload()
+
+# Serving workload: 32 resident obstacles of 1k-200k triangles and the same
+# 20k-triangle link; requests come from paper_2012_05348_amd.serve.make_requests
+# with a generator seeded by rng_for(4, 2).
+SERVING = BatchedWorkload(index=4, n_obstacles=32, min_poses=0)
