@@ -61,6 +61,7 @@ cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
     d.K = h.K;
     d.leaf_size = h.leaf_size;
     d.depth = h.depth;
+    d.branching = h.branching;
     d.max_abs = h.max_abs_coord;
     return d;
 }
@@ -165,6 +166,12 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.A = dev_view(a, a_dev);
     if (obs) {
         q.B = obs->host[0];
+        // launch decisions that depend on the fixed model use the set's largest
+        // depth and branching factor (each unit loads its own model's view)
+        for (const cbvh::DevModel &d : obs->host) {
+            q.B.depth = d.depth > q.B.depth ? d.depth : q.B.depth;
+            q.B.branching = d.branching > q.B.branching ? d.branching : q.B.branching;
+        }
         q.Btab = obs->dev_table;
         q.pose_obj = pose_obj;
         q.n_obj = obs->n;

@@ -19,7 +19,7 @@ struct DevModel {
     const float *tris;
     const uint32_t *perm;
     const uint32_t *treelets;
-    uint32_t n_nodes, n_tris, n_treelets, stride, bits, K, leaf_size, depth;
+    uint32_t n_nodes, n_tris, n_treelets, stride, bits, K, leaf_size, depth, branching;
     float max_abs;
 };
 
@@ -101,6 +101,7 @@ struct QueryArgs {
     uint32_t pair_cap;
     uint32_t no_split;  // never donate work; exhausting the LDS stack then fails the pose
     uint32_t max_pop;   // entries one node step may pop (1..8)
+    uint32_t pop_reserve;  // multi-entry steps must leave room for the rest of a descent
     uint32_t donate_min_steps;  // a unit feeds waiting waves only after this many steps
     uint32_t max_helpers;       // waves that stay to take items once the poses are gone
     uint32_t donate_period;     // node steps between two looks at the item queue

@@ -973,15 +973,17 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 my_nb = topo_leaf(my_pB) ? 1u : topo_count(my_pB);
                 if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_na = my_nb = 0;  // culled
             }
-            // inclusive prefix over lanes 0..PMAX-1 of (A records, B records, tests), packed in one word
+            // inclusive prefix over lanes 0..PMAX-1 of (A records, B records, tests,
+            // expanded entries), packed in one word (8, 8, 10 and 6 bits)
             const uint32_t my_tk = my_na * my_nb;
-            const uint32_t my_pk = lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16)) : 0u;
+            const uint32_t my_pk =
+                lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16) | ((my_tk > 0 ? 1u : 0u) << 26)) : 0u;
             uint32_t pk = my_pk;
             static_assert(PMAX == 8, "the scan covers 8 lanes");
             pk += row_shr<1>(pk);
             pk += row_shr<2>(pk);
             pk += row_shr<4>(pk);
-            const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = pk >> 16;
+            const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = (pk >> 16) & 0x3FFu, inX = pk >> 26;
             // with lane+1 entries popped the new frame sits on top of the frame of
             // the next remaining entry, which lane+1 has read
             const uint32_t nx_e = row_shl<1>(my_e), nx_fend = row_shl<1>(my_fend);
@@ -991,12 +993,21 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             // proximity queries dive one expansion at a time until a first leaf
             // distance exists: without a bound nothing is culled
             const bool dive = MODE == MODE_DIST && best32 == INFINITY;
-            // (a frame stays live while any of its entries is pending, so wider
-            // frames pin more records: one test pass per step keeps frames small)
-            const bool ok = lane < q.max_pop && lane < top && (!dive || lane == 0) && inA <= AMAX &&
+            // A frame stays live while any of its entries is pending, so a wider
+            // frame pins records for its whole subtree.  Where the record space
+            // cannot hold a full-depth descent (the host decides), more than
+            // one entry is popped only while the new frame leaves room for a
+            // frame of the top entry's size at every level a descent below it
+            // can still take (the two trees' depths minus the new frame's level).
+            const uint32_t levels = MA.depth + MB.depth;
+            const uint32_t reserve = (lane == 0 || !q.pop_reserve)
+                                         ? 0u
+                                         : lane_of(my_na + my_nb, 0) * (levels > nid_l ? levels - nid_l : 0u);
+            // culled entries (distance queries) cost nothing and may always go
+            const bool ok = lane < (uint32_t)PMAX && inX <= q.max_pop && lane < top && (!dive || lane == 0) && inA <= AMAX &&
                             inA + inB <= (uint32_t)WAVE && inT <= TMAX && rem_l + inT <= lim.entries &&
                             lq_count + inT <= lim.leafq && nid_l < (uint32_t)MAX_FRAMES &&
-                            nbase_l + inA + inB <= lim.records && nbase_l + inA + inB <= REC_MASK + 1u;
+                            nbase_l + inA + inB + reserve <= lim.records && nbase_l + inA + inB <= REC_MASK + 1u;
             const uint32_t n_pop = (uint32_t)__builtin_ctzll(~__ballot(ok));  // leading lanes that fit
             if (n_pop == 0) {
                 // not even the top entry fits the LDS state: hand every pending
@@ -1014,6 +1025,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             const int last = (int)n_pop - 1;
             const uint32_t nA_tot = lane_of(inA, last), total_rec = nA_tot + lane_of(inB, last);
             const uint32_t tasks_tot = lane_of(inT, last);
+            static_assert(TMAX < 1024u && PMAX < 64, "packed prefix fields");
             const uint32_t new_base = lane_of(nbase_l, last), new_id = lane_of(nid_l, last);
             top -= n_pop;
             // popped entries with tests to run get a meta word each; culled ones drop out
@@ -1024,7 +1036,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             if (act) {
                 const uint32_t ex = pk - my_pk;  // exclusive prefix
                 const uint32_t slot = mbcnt(m_act);
-                meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, ex >> 16);
+                meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
             }
             {
                 uint32_t nbytes = 0;
@@ -1405,6 +1417,11 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // without donation a wave beyond the pose count has nothing to do
     if (q.no_split && grid > q.n_poses) grid = q.n_poses;
     QueryArgs qq = q;
+    // Multi-entry node steps pop freely where the record space holds one
+    // expansion frame (both branching factors) at every level of the two
+    // trees; elsewhere each such step keeps room for the rest of a descent.
+    const uint32_t full_descent = 2u + (q.A.depth + q.B.depth) * (q.A.branching + q.B.branching);
+    qq.pop_reserve = lim.records >= full_descent ? 0u : 1u;
     qq.max_pop = min(env_u32("CBVH_MAX_POP", (uint32_t)PMAX), (uint32_t)PMAX);
     qq.donate_min_steps = env_u32("CBVH_DONATE_MIN_STEPS", kDonateMinSteps);
     qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * kHelpersPerCu);

@@ -116,7 +116,7 @@ class Server:
     """Continuous-batching request loop over a resident obstacle set."""
 
     def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
-                 memory_budget=2 << 30, max_poses=None):
+                 memory_budget=2 << 30, max_poses=None, launch_cap=16384):
         self.link, self.obstacles, self.device = link, obstacles, device
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
@@ -129,7 +129,8 @@ class Server:
                     lo = mid
                 else:
                     hi = mid - 1
-            max_poses = lo
+            # larger launches add latency and little throughput
+            max_poses = min(lo, launch_cap)
         self.max_poses = max_poses
         self.slots = [_Slot(link, k, max_poses, device) for k in (COLLIDE, DISTANCE) for _ in range(slots_per_kind)]
 
