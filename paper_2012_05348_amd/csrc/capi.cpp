@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <new>
 #include <string>
@@ -77,7 +78,7 @@ cbvh::StackLimits current_limits(uint32_t K, int mode)
 
 // workspace carving: [header | item queue | per-pose answers | pair buffers]
 struct WsPlan {
-    uint64_t hdr, items, ready, hitw, fix, best32, best64, pair_raw, pair_cnt, pair_cursor, pair_keys, total;
+    uint64_t hdr, wave_ctr, items, ready, hitw, fix, best32, best64, pair_raw, pair_cnt, pair_cursor, pair_keys, total;
     uint32_t item_cap, item_words, fix_cap;
 };
 
@@ -98,6 +99,7 @@ WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
     p.item_cap = (uint32_t)cap;
     bool dist = mode == cbvh::MODE_DIST, pairs = mode == cbvh::MODE_PAIRS;
     p.hdr = take(sizeof(cbvh::WsHeader));
+    p.wave_ctr = take(8ull * cbvh::C_NUM * cbvh::kMaxWaves);
     p.items = take((uint64_t)p.item_cap * p.item_words * 4ull);
     p.ready = take(4ull * p.item_cap);
     p.hitw = take(mode == cbvh::MODE_BOOL ? 4ull * n : 0);
@@ -187,6 +189,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.pair_cap = pair_cap;
     q.no_split = (flags & CBVH_NO_SPLIT) ? 1u : 0u;
     q.ws.hdr = (cbvh::WsHeader *)(w + plan.hdr);
+    q.ws.wave_ctr = (unsigned long long *)(w + plan.wave_ctr);
     q.ws.items = (uint32_t *)(w + plan.items);
     q.ws.ready = (uint32_t *)(w + plan.ready);
     q.ws.item_cap = plan.item_cap;
@@ -428,29 +431,49 @@ cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, 
 cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream)
 {
     if (!workspace || !out) return fail(CBVH_E_INVALID, "NULL argument");
-    if (workspace_bytes < sizeof(cbvh::WsHeader)) return fail(CBVH_E_CAPACITY, "workspace too small");
+    const size_t row_bytes = 8ull * cbvh::C_NUM, rows_at = align_up(sizeof(cbvh::WsHeader), 256);
+    if (workspace_bytes < rows_at) return fail(CBVH_E_CAPACITY, "workspace too small");
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
     cbvh::WsHeader h;
     e = hipMemcpy(&h, workspace, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
     memset(out, 0, sizeof *out);
-    out->bv_tests = h.counters[cbvh::C_BV_TESTS];
-    out->tri_tests = h.counters[cbvh::C_TRI_TESTS];
-    out->tri_fp64 = h.counters[cbvh::C_TRI_FP64];
-    out->expansions = h.counters[cbvh::C_EXPANSIONS];
-    out->node_bytes = h.counters[cbvh::C_NODE_BYTES];
-    out->tri_bytes = h.counters[cbvh::C_TRI_BYTES];
-    out->donated_items = h.counters[cbvh::C_DONATED];
-    out->max_entries = h.counters[cbvh::C_MAX_ENTRIES];
-    out->max_records = h.counters[cbvh::C_MAX_RECORDS];
-    out->t_start = h.counters[cbvh::C_T_START];
-    out->t_drain = h.counters[cbvh::C_T_DRAIN];
-    out->t_end = h.counters[cbvh::C_T_END];
-    out->max_pose_steps = h.counters[cbvh::C_MAX_POSE_STEPS];
     out->wait_timeouts = h.error;
-    out->node_steps = h.counters[cbvh::C_NODE_STEPS];
-    out->leaf_steps = h.counters[cbvh::C_LEAF_STEPS];
+    const uint32_t nw = h.n_waves;
+    if (nw == 0) return CBVH_OK;  // no traversal launch has run on this workspace
+    if (nw > cbvh::kMaxWaves || workspace_bytes < rows_at + nw * row_bytes)
+        return fail(CBVH_E_CAPACITY, "workspace too small for the launch's counter rows");
+    std::vector<unsigned long long> rows((size_t)nw * cbvh::C_NUM);
+    e = hipMemcpy(rows.data(), (const char *)workspace + rows_at, rows.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(e, "hipMemcpy");
+    unsigned long long c[cbvh::C_NUM];
+    for (int k = 0; k < cbvh::C_NUM; k++) {
+        const bool is_min = k == cbvh::C_T_START || k == cbvh::C_T_DRAIN;
+        const bool is_max = k == cbvh::C_MAX_ENTRIES || k == cbvh::C_MAX_RECORDS || k == cbvh::C_MAX_POSE_STEPS ||
+                            k == cbvh::C_T_END;
+        unsigned long long v = is_min ? ~0ull : 0ull;
+        for (uint32_t w = 0; w < nw; w++) {
+            const unsigned long long x = rows[(size_t)w * cbvh::C_NUM + k];
+            v = is_min ? std::min(v, x) : is_max ? std::max(v, x) : v + x;
+        }
+        c[k] = v;
+    }
+    out->bv_tests = c[cbvh::C_BV_TESTS];
+    out->tri_tests = c[cbvh::C_TRI_TESTS];
+    out->tri_fp64 = c[cbvh::C_TRI_FP64];
+    out->expansions = c[cbvh::C_EXPANSIONS];
+    out->node_bytes = c[cbvh::C_NODE_BYTES];
+    out->tri_bytes = c[cbvh::C_TRI_BYTES];
+    out->donated_items = c[cbvh::C_DONATED];
+    out->max_entries = c[cbvh::C_MAX_ENTRIES];
+    out->max_records = c[cbvh::C_MAX_RECORDS];
+    out->t_start = c[cbvh::C_T_START];
+    out->t_drain = c[cbvh::C_T_DRAIN];
+    out->t_end = c[cbvh::C_T_END];
+    out->max_pose_steps = c[cbvh::C_MAX_POSE_STEPS];
+    out->node_steps = c[cbvh::C_NODE_STEPS];
+    out->leaf_steps = c[cbvh::C_LEAF_STEPS];
     return CBVH_OK;
 }
 

@@ -23,7 +23,8 @@ struct DevModel {
     float max_abs;
 };
 
-// Counters kept in the workspace header (order matches cbvh_stats_t).
+// Per-wave counters (order matches cbvh_stats_t); each wave writes its own
+// row once, when it exits, and the host reduces the rows.
 enum Counter : int {
     C_BV_TESTS = 0,
     C_TRI_TESTS,
@@ -43,21 +44,25 @@ enum Counter : int {
     C_NUM = 16
 };
 
+// Most waves one traversal launch may have (rows of per-wave counters).
+constexpr uint32_t kMaxWaves = 8192;
+
 // Start of every workspace.  The queue words that many waves hammer at
-// once sit on cache lines of their own.
+// once sit on cache lines of their own; the per-wave counter rows
+// (kMaxWaves x C_NUM u64) follow the header.
 struct WsHeader {
-    unsigned long long counters[C_NUM];
     uint32_t pose_next;   // persistent-wave pose queue
     uint32_t pair_count;  // pairs appended (may exceed capacity)
     uint32_t error;       // a wave gave up waiting for an item (never expected)
     uint32_t fix_count;   // leaf pairs handed to the FP64 stage (may exceed capacity)
-    uint32_t helpers;     // waves that found the pose queue empty
+    uint32_t n_waves;     // waves of the traversal launch (rows of per-wave counters)
     uint32_t pad0[27];
     uint32_t q_head;      // next item slot to claim (8-byte aligned: read together with q_tail)
     uint32_t q_tail;      // next item slot to reserve
     uint32_t pad1[30];
     uint32_t pending;     // poses + published items not yet finished
     uint32_t pad2[31];
+    uint32_t pad3[32];
 };
 static_assert(sizeof(WsHeader) == 512, "workspace header size");
 
@@ -70,6 +75,7 @@ struct StackLimits {
 
 struct Workspace {
     WsHeader *hdr;
+    unsigned long long *wave_ctr;  // [kMaxWaves][C_NUM] per-wave counters
     uint32_t *items;          // donated work items, item_words dwords each
     uint32_t *ready;          // [item_cap] non-zero once an item is published
     uint32_t item_cap;        // item slots (slot indices are never reused within a query)
@@ -103,9 +109,11 @@ struct QueryArgs {
     uint32_t max_pop;   // entries one node step may pop (1..8)
     uint32_t pop_reserve;  // multi-entry steps must leave room for the rest of a descent
     uint32_t donate_min_steps;  // a unit feeds waiting waves only after this many steps
-    uint32_t max_helpers;       // waves that stay to take items once the poses are gone
+    uint32_t max_helpers;       // waves (the lowest block indices) that stay to take items once the poses are gone
     uint32_t donate_period;     // node steps between two looks at the item queue
     uint32_t donate_keep;       // entries a donor keeps at least (0 = half of its stack)
+    uint32_t donate_min_top;    // a unit feeds waiting waves only with at least this many entries
+    uint32_t max_donate;        // entries one look at the item queue may hand over
     Workspace ws;
 };
 

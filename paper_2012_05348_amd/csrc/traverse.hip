@@ -212,54 +212,75 @@ __device__ void pose_setup(const float *P, float maxA, float4 *xf, uint32_t lane
     xf[2 * lane + 1] = make_float4(__double2float_ru(vt + pad), __double2float_rd(vt - pad), 0.0f, 0.0f);
 }
 
+// Reads of model data through global-address-space pointers: the model
+// pointers reach the kernel through structures in memory (and through
+// selects between the two models), so the compiler would otherwise emit
+// flat loads, whose waits also drain every outstanding LDS access.
+template <typename T>
+__device__ __forceinline__ T gload(const void *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+// Raw descriptor words of one node: K 16-bit code pairs (one word each),
+// K 8-bit code pairs (one 16-bit load each), K binary16 pairs, or 2K FP32
+// bounds.  All of them are read up front, before the topology word is
+// known, so that a node costs one memory round trip.
+template <int K, int BITS>
+struct NodeWords {
+    static constexpr int N = BITS == 0 ? 2 * K : K;
+    uint32_t w[N];
+};
+
+template <int K, int BITS>
+__device__ __forceinline__ void load_node(const DevModel &M, uint32_t node, uint32_t &topo, NodeWords<K, BITS> &nw)
+{
+    const uint8_t *code = M.codes + (size_t)node * M.stride;
+#pragma unroll
+    for (int k = 0; k < NodeWords<K, BITS>::N; k++)
+        nw.w[k] = BITS == 8 ? (uint32_t)gload<uint16_t>(code + 2 * k) : gload<uint32_t>(code + 4 * k);
+    topo = gload<uint32_t>(M.topo + node);
+    // keep the compiler from sinking the code-word loads behind the branch
+    // on the topology word (which would serialise two round trips)
+#pragma unroll
+    for (int k = 0; k < NodeWords<K, BITS>::N; k++) asm volatile("" : "+v"(nw.w[k]));
+}
+
 // Decode one node's 2K bounds (lo, hi per slab) from its parent's decoded
 // bounds: E = Ph - Pl, s = E * 2^-BITS (0 if E < 2^-100), lo = fma(ql, s, Pl),
 // hi = fma(-qh, s, Ph).  Absolute nodes (treelet tops) and uncompressed
 // models read FP32 bounds instead, half-precision models binary16 bounds.
 template <int K, int BITS, typename ParentPtr>
-__device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, uint32_t topo, ParentPtr parent,
-                                            float out[2 * K])
+__device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
+                                             ParentPtr parent, float out[2 * K])
 {
-    const uint8_t *code = M.codes + (size_t)node * M.stride;
     if constexpr (BITS == (int)kBitsFp16) {
         // binary16 absolute bounds, widened exactly
-        const _Float16 *h = (const _Float16 *)code;
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            out[2 * k] = (float)h[2 * k];
-            out[2 * k + 1] = (float)h[2 * k + 1];
+            out[2 * k] = (float)__builtin_bit_cast(_Float16, (uint16_t)(nw.w[k] & 0xFFFFu));
+            out[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(nw.w[k] >> 16));
         }
     } else if constexpr (BITS == 0) {
-        const float2 *c = (const float2 *)code;
 #pragma unroll
-        for (int k = 0; k < K; k++) {
-            float2 w = c[k];
-            out[2 * k] = w.x;
-            out[2 * k + 1] = w.y;
-        }
+        for (int k = 0; k < 2 * K; k++) out[k] = __uint_as_float(nw.w[k]);
     } else if (topo_abs(topo)) {
-        uint32_t ai = *(const uint32_t *)code;
-        const float2 *c = (const float2 *)(M.absb + (size_t)ai * 2 * K);
+        // the first four code bytes hold the node's index in the FP32 table
+        const uint32_t ai = BITS == 8 ? (nw.w[0] | (nw.w[1] << 16)) : nw.w[0];
+        const uint64_t *c = (const uint64_t *)(M.absb + (size_t)ai * 2 * K);
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            float2 w = c[k];
-            out[2 * k] = w.x;
-            out[2 * k + 1] = w.y;
+            const uint64_t w = gload<uint64_t>(c + k);
+            out[2 * k] = __uint_as_float((uint32_t)w);
+            out[2 * k + 1] = __uint_as_float((uint32_t)(w >> 32));
         }
     } else {
         const float scale = 1.0f / (float)(1u << (BITS & 31));
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            uint32_t ql, qh;
-            if (BITS == 8) {
-                uint32_t w = *(const uint16_t *)(code + 2 * k);
-                ql = w & 0xFFu;
-                qh = w >> 8;
-            } else {
-                uint32_t w = *(const uint32_t *)(code + 4 * k);
-                ql = w & 0xFFFFu;
-                qh = w >> 16;
-            }
+            const uint32_t w = nw.w[k];
+            const uint32_t ql = BITS == 8 ? (w & 0xFFu) : (w & 0xFFFFu);
+            const uint32_t qh = BITS == 8 ? (w >> 8) : (w >> 16);
             float Pl = parent[2 * k], Ph = parent[2 * k + 1];
             float E = Ph - Pl;
             float s = E >= 0x1p-100f ? E * scale : 0.0f;
@@ -269,11 +290,21 @@ __device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, ui
     }
 }
 
+template <int K, int BITS, typename ParentPtr>
+__device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, ParentPtr parent, float out[2 * K])
+{
+    NodeWords<K, BITS> nw;
+    uint32_t topo;
+    load_node<K, BITS>(M, node, topo, nw);
+    decode_words<K, BITS>(M, topo, nw, parent, out);
+}
+
 __device__ __forceinline__ void load_tri(const float *tris, uint32_t i, V3<float> t[3])
 {
     const float *p = tris + 9 * (size_t)i;
 #pragma unroll
-    for (int v = 0; v < 3; v++) t[v] = {p[3 * v], p[3 * v + 1], p[3 * v + 2]};
+    for (int v = 0; v < 3; v++)
+        t[v] = {gload<float>(p + 3 * v), gload<float>(p + 3 * v + 1), gload<float>(p + 3 * v + 2)};
 }
 
 struct Pose {
@@ -361,6 +392,8 @@ constexpr uint32_t kDonatePeriod = 8;
 constexpr uint32_t kSyncPeriod = 4;
 // most items one balancing donation hands out
 constexpr uint32_t kMaxDonate = 32;
+// a unit hands work over only while it holds at least this many entries
+constexpr uint32_t kDonateMinTop = 2;
 // pose word of a queue slot that holds no work
 constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 
@@ -466,7 +499,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         return ok ? n : 0u;
     };
 
-    bool poses_left = true, helper = false;
+    bool poses_left = true;
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
     float e_abs = 0.0f, e_sph = 0.0f;
@@ -492,13 +525,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         }
         if (!poses_left) {
             if (!can_donate) break;
-            if (!helper) {
-                // the first time: stay as a helper only while few enough do
-                uint32_t hn = 0;
-                if (lane == 0) hn = rmw_add(&hdr->helpers, 1u);
-                if (uni(hn) >= q.max_helpers) break;
-                helper = true;
-            }
+            // the waves with the lowest block indices (spread over the XCDs
+            // and CUs by the dispatcher) stay as helpers; the others exit
+            if (blockIdx.x >= q.max_helpers) break;
             uint32_t slot = 0;
             if (lane == 0) slot = rmw_add(&hdr->q_head, 1u);
             slot = uni(slot);
@@ -592,9 +621,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             // root frame: record 0 = A's root, record 1 = B's root; the root pair is tested first
             if (lane < 2) {
                 const DevModel &M = lane == 0 ? MA : MB;
-                uint32_t tw = M.topo[0];
+                NodeWords<K, BITS> nw;
+                uint32_t tw;
+                load_node<K, BITS>(M, 0, tw, nw);
                 float bnd[2 * K];
-                decode_node<K, BITS>(M, 0, tw, (const float *)nullptr, bnd);
+                decode_words<K, BITS>(M, tw, nw, (const float *)nullptr, bnd);
                 rtopo[lane] = tw;
 #pragma unroll
                 for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
@@ -925,14 +956,14 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             if (top == 0) break;
 
             // -------- feed waiting waves with the bottom of the stack --------
-            if (can_donate && top >= 2 && steps >= next_look && steps >= q.donate_min_steps) {
+            if (can_donate && top >= q.donate_min_top && steps >= next_look && steps >= q.donate_min_steps) {
                 next_look = steps + q.donate_period;
                 uint32_t want = 0;
                 if (lane == 0) {
                     unsigned long long ht = poll64((unsigned long long *)&hdr->q_head);
                     uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
                     const uint32_t share = q.donate_keep ? (top > q.donate_keep ? top - q.donate_keep : 0u) : top / 2;
-                    want = h > t ? min(h - t, min(share, kMaxDonate)) : 0u;
+                    want = h > t ? min(h - t, min(share, q.max_donate)) : 0u;
                 }
                 want = uni(want);
                 if (want && publish(pose, want, want, best32) == want) {
@@ -1080,8 +1111,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 } else {
                     const DevModel &M = sideA ? MA : MB;
                     const uint32_t node = topo_first(ptopo) + c;
-                    my_topo = M.topo[node];
-                    decode_node<K, BITS>(M, node, my_topo, pb, my_b);
+                    NodeWords<K, BITS> nw;
+                    load_node<K, BITS>(M, node, my_topo, nw);
+                    decode_words<K, BITS>(M, my_topo, nw, pb, my_b);
                 }
             }
             wave_sync();
@@ -1122,23 +1154,31 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         }
         wave_sync();
     }
-    // ---- flush counters ----
-    if (lane == 0) {
-        atomicAdd(&hdr->counters[C_BV_TESTS], cnt.bv_tests);
-        atomicAdd(&hdr->counters[C_TRI_TESTS], cnt.tri_tests);
-        atomicAdd(&hdr->counters[C_TRI_FP64], cnt.tri_fp64);
-        atomicAdd(&hdr->counters[C_EXPANSIONS], cnt.expansions);
-        atomicAdd(&hdr->counters[C_NODE_BYTES], cnt.node_bytes);
-        atomicAdd(&hdr->counters[C_TRI_BYTES], cnt.tri_bytes);
-        atomicAdd(&hdr->counters[C_DONATED], cnt.donated);
-        atomicAdd(&hdr->counters[C_NODE_STEPS], cnt.node_steps);
-        atomicAdd(&hdr->counters[C_LEAF_STEPS], cnt.leaf_steps);
-        atomicMax(&hdr->counters[C_MAX_ENTRIES], (unsigned long long)cnt.max_entries);
-        atomicMax(&hdr->counters[C_MAX_RECORDS], (unsigned long long)cnt.max_records);
-        atomicMax(&hdr->counters[C_MAX_POSE_STEPS], (unsigned long long)cnt.max_steps);
-        if (t_first) atomicMin(&hdr->counters[C_T_START], t_first);
-        atomicMin(&hdr->counters[C_T_DRAIN], t_drain);
-        atomicMax(&hdr->counters[C_T_END], (unsigned long long)wall_clock64());
+    // ---- this wave's counter row (plain stores: thousands of waves exit
+    // at about the same time, and atomics on one line would serialise) ----
+    if (blockIdx.x == 0 && lane == 0) hdr->n_waves = gridDim.x;
+    const unsigned long long t_exit = wall_clock64();
+    if (lane < (uint32_t)C_NUM) {
+        unsigned long long v = 0;
+        switch (lane) {
+        case C_BV_TESTS: v = cnt.bv_tests; break;
+        case C_TRI_TESTS: v = cnt.tri_tests; break;
+        case C_TRI_FP64: v = cnt.tri_fp64; break;
+        case C_EXPANSIONS: v = cnt.expansions; break;
+        case C_NODE_BYTES: v = cnt.node_bytes; break;
+        case C_TRI_BYTES: v = cnt.tri_bytes; break;
+        case C_DONATED: v = cnt.donated; break;
+        case C_MAX_ENTRIES: v = cnt.max_entries; break;
+        case C_MAX_RECORDS: v = cnt.max_records; break;
+        case C_T_START: v = t_first ? t_first : ~0ull; break;
+        case C_T_DRAIN: v = t_drain ? t_drain : ~0ull; break;
+        case C_T_END: v = t_exit; break;
+        case C_MAX_POSE_STEPS: v = cnt.max_steps; break;
+        case C_NODE_STEPS: v = cnt.node_steps; break;
+        case C_LEAF_STEPS: v = cnt.leaf_steps; break;
+        default: break;
+        }
+        q.ws.wave_ctr[(size_t)blockIdx.x * C_NUM + lane] = v;
     }
 }
 // ---------------------------------------------------------------------------
@@ -1150,8 +1190,7 @@ __global__ void init_kernel(WsHeader *hdr, uint8_t *hit, uint8_t *status, unsign
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < sizeof(WsHeader) / 4) {
-        bool is_min = i / 2 == C_T_START || i / 2 == C_T_DRAIN;  // 64-bit counters that take minima
-        uint32_t v = is_min ? 0xFFFFFFFFu : 0u;
+        uint32_t v = 0;
         if (i == offsetof(WsHeader, pending) / 4) v = n;  // every pose is pending
         ((uint32_t *)hdr)[i] = v;
     }
@@ -1348,7 +1387,7 @@ __global__ void decode_all_kernel(DevModel M, float *out)
         // absolute descriptors (FP32 or FP16): one thread per node
         for (uint32_t i = t; i < M.n_nodes; i += gridDim.x * blockDim.x) {
             float b[2 * K];
-            decode_node<K, BITS>(M, i, M.topo[i], (const float *)nullptr, b);
+            decode_node<K, BITS>(M, i, (const float *)nullptr, b);
             for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
         }
         return;
@@ -1359,7 +1398,7 @@ __global__ void decode_all_kernel(DevModel M, float *out)
         uint32_t w = M.topo[i];
         if (topo_abs(w)) {
             float b[2 * K];
-            decode_node<K, BITS>(M, i, w, (const float *)nullptr, b);
+            decode_node<K, BITS>(M, i, (const float *)nullptr, b);
             for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
         }
         if (!topo_leaf(w)) {
@@ -1368,7 +1407,7 @@ __global__ void decode_all_kernel(DevModel M, float *out)
             for (uint32_t c = 0; c < nc; c++) {
                 uint32_t node = c0 + c;
                 float b[2 * K];
-                decode_node<K, BITS>(M, node, M.topo[node], out + (size_t)i * 2 * K, b);
+                decode_node<K, BITS>(M, node, out + (size_t)i * 2 * K, b);
                 for (int k = 0; k < 2 * K; k++) out[(size_t)node * 2 * K + k] = b[k];
             }
         }
@@ -1416,6 +1455,7 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     uint32_t grid = (uint32_t)cus * per_cu;
     // without donation a wave beyond the pose count has nothing to do
     if (q.no_split && grid > q.n_poses) grid = q.n_poses;
+    if (grid > kMaxWaves) grid = kMaxWaves;  // rows of per-wave counters in the workspace
     QueryArgs qq = q;
     // Multi-entry node steps pop freely where the record space holds one
     // expansion frame (both branching factors) at every level of the two
@@ -1427,6 +1467,8 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * kHelpersPerCu);
     qq.donate_period = env_u32("CBVH_DONATE_PERIOD", kDonatePeriod);
     qq.donate_keep = env_u32("CBVH_DONATE_KEEP", 1u) == 1u ? 0u : env_u32("CBVH_DONATE_KEEP", 1u);
+    qq.donate_min_top = max(env_u32("CBVH_DONATE_MIN_TOP", kDonateMinTop), 2u);
+    qq.max_donate = max(min(env_u32("CBVH_MAX_DONATE", kMaxDonate), kMaxDonate), 1u);
     hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, qq, lim);
     return hipGetLastError();
 }
