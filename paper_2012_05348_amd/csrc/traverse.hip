@@ -499,7 +499,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         return ok ? n : 0u;
     };
 
-    bool poses_left = true;
+    bool poses_left = true, first_claim = true;
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
     float e_abs = 0.0f, e_sph = 0.0f;
@@ -514,13 +514,19 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         uint32_t it_tA = 0, it_tB = 0;
         float it_lb = 0.0f;
         if (poses_left) {
-            uint32_t p = 0;
-            if (lane == 0) p = atomicAdd(&hdr->pose_next, 1u);
+            // a wave's first pose is its block index; later ones come from
+            // the queue (no burst of atomics on one line at the start)
+            uint32_t p = blockIdx.x;
+            if (!first_claim && lane == 0) p = gridDim.x + atomicAdd(&hdr->pose_next, 1u);
+            first_claim = false;
             pose = uni(p);
             if (t_first == 0) t_first = wall_clock64();
             if (pose >= q.n_poses) {
                 poses_left = false;
                 t_drain = wall_clock64();
+                // this wave starts no more poses: it no longer counts as work
+                // that could still publish items
+                if (can_donate && lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
             }
         }
         if (!poses_left) {
@@ -579,10 +585,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 // batched query: this pose's fixed model
                 const uint32_t obj = uni(q.pose_obj[pose]);
                 if (obj >= q.n_obj) {
-                    if (lane == 0) {
-                        q.status[pose] = 4;  // CBVH_POSE_BAD_OBSTACLE
-                        if (can_donate) rmw_add(&hdr->pending, 0xFFFFFFFFu);
-                    }
+                    if (lane == 0) q.status[pose] = 4;  // CBVH_POSE_BAD_OBSTACLE
                     continue;
                 }
                 MB = q.Btab[obj];
@@ -1150,7 +1153,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     __hip_atomic_fetch_min(&q.ws.best64[pose], (unsigned long long)__double_as_longlong(best64),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (can_donate) rmw_add(&hdr->pending, 0xFFFFFFFFu);  // this unit is finished
+            if (from_item) rmw_add(&hdr->pending, 0xFFFFFFFFu);  // this item is finished
         }
         wave_sync();
     }
@@ -1186,12 +1189,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
 // ---------------------------------------------------------------------------
 __global__ void init_kernel(WsHeader *hdr, uint8_t *hit, uint8_t *status, unsigned int *best32,
                             unsigned long long *best64, uint32_t *pair_cnt, uint32_t *pair_cursor, uint32_t *hitw,
-                            uint32_t *ready, uint32_t n_ready, uint32_t n)
+                            uint32_t *ready, uint32_t n_ready, uint32_t n, uint32_t pending0)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < sizeof(WsHeader) / 4) {
         uint32_t v = 0;
-        if (i == offsetof(WsHeader, pending) / 4) v = n;  // every pose is pending
+        if (i == offsetof(WsHeader, pending) / 4) v = pending0;  // every wave holds work until it drains
         ((uint32_t *)hdr)[i] = v;
     }
     if (i < n_ready) ready[i] = 0;
@@ -1418,13 +1421,15 @@ __global__ void decode_all_kernel(DevModel M, float *out)
 // CBVH_MAX_POP (entries per node step), CBVH_DONATE_MIN_STEPS,
 // CBVH_MAX_HELPERS.
 //
-// Once the pose queue is empty only a few waves stay to take donated work
-// (one per CU): every wave that stays competes for issue slots with the
-// long units on the critical path, and units feed them only after some
-// steps, so that units about to finish do not split needlessly.  Measured
-// on MI355X over the collision and proximity workloads.
+// Once the pose queue is empty only some waves stay to take donated work:
+// every wave that stays competes for issue slots with the long units on the
+// critical path, and units feed them only after some steps, so that units
+// about to finish do not split needlessly.  Early-exit collision queries
+// have short tails (one helper per CU), pair lists longer ones (two), and
+// branch-and-bound distance queries the longest (four).  Measured on MI355X
+// over the collision, pair-list and proximity workloads.
 constexpr uint32_t kDonateMinSteps = 16;
-constexpr uint32_t kHelpersPerCu = 1;
+constexpr uint32_t helpers_per_cu(int mode) { return mode == MODE_DIST ? 4u : mode == MODE_PAIRS ? 2u : 1u; }
 uint32_t env_u32(const char *name, uint32_t dflt)
 {
     const char *v = getenv(name);
@@ -1456,6 +1461,22 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // without donation a wave beyond the pose count has nothing to do
     if (q.no_split && grid > q.n_poses) grid = q.n_poses;
     if (grid > kMaxWaves) grid = kMaxWaves;  // rows of per-wave counters in the workspace
+    {
+        // workspace init: header (pending work = the waves, each until it
+        // finds the pose queue empty), per-pose outputs, and the item
+        // queue's ready flags (its slots are numbered from 0 in every query)
+        const uint32_t n = q.n_poses;
+        const bool dist = q.mode == MODE_DIST, pairs = q.mode == MODE_PAIRS;
+        const uint32_t n_ready = q.no_split ? 0u : q.ws.item_cap;
+        uint32_t threads = 256, items = max(max(n, n_ready), (uint32_t)(sizeof(WsHeader) / 4));
+        hipLaunchKernelGGL(init_kernel, dim3((items + threads - 1) / threads), dim3(threads), 0, s, q.ws.hdr,
+                           dist ? nullptr : q.hit, q.status, dist ? q.ws.best32 : nullptr,
+                           dist ? q.ws.best64 : nullptr, pairs ? q.ws.pair_cnt : nullptr,
+                           pairs ? q.ws.pair_cursor : nullptr, q.mode == MODE_BOOL ? q.ws.hitw : nullptr, q.ws.ready,
+                           n_ready, n, q.no_split ? 0u : grid);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     QueryArgs qq = q;
     // Multi-entry node steps pop freely where the record space holds one
     // expansion frame (both branching factors) at every level of the two
@@ -1464,7 +1485,7 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     qq.pop_reserve = lim.records >= full_descent ? 0u : 1u;
     qq.max_pop = min(env_u32("CBVH_MAX_POP", (uint32_t)PMAX), (uint32_t)PMAX);
     qq.donate_min_steps = env_u32("CBVH_DONATE_MIN_STEPS", kDonateMinSteps);
-    qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * kHelpersPerCu);
+    qq.max_helpers = env_u32("CBVH_MAX_HELPERS", (uint32_t)cus * helpers_per_cu(MODE));
     qq.donate_period = env_u32("CBVH_DONATE_PERIOD", kDonatePeriod);
     qq.donate_keep = env_u32("CBVH_DONATE_KEEP", 1u) == 1u ? 0u : env_u32("CBVH_DONATE_KEEP", 1u);
     qq.donate_min_top = max(env_u32("CBVH_DONATE_MIN_TOP", kDonateMinTop), 2u);
@@ -1517,19 +1538,7 @@ hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t 
 {
     const uint32_t n = q.n_poses;
     const bool dist = q.mode == MODE_DIST, pairs = q.mode == MODE_PAIRS;
-    {
-        // the item queue's ready flags start clear (its slots are numbered
-        // from 0 in every query)
-        const uint32_t n_ready = q.no_split ? 0u : q.ws.item_cap;
-        uint32_t threads = 256, items = max(max(n, n_ready), (uint32_t)(sizeof(WsHeader) / 4));
-        hipLaunchKernelGGL(init_kernel, dim3((items + threads - 1) / threads), dim3(threads), 0, s, q.ws.hdr,
-                           dist ? nullptr : q.hit, q.status, dist ? q.ws.best32 : nullptr,
-                           dist ? q.ws.best64 : nullptr, pairs ? q.ws.pair_cnt : nullptr,
-                           pairs ? q.ws.pair_cursor : nullptr, q.mode == MODE_BOOL ? q.ws.hitw : nullptr, q.ws.ready,
-                           n_ready, n);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    // workspace init and the traversal (the init needs the traversal's grid)
     hipError_t e = launch_any(q, lim, s);
     if (e != hipSuccess) return e;
     {
