@@ -112,7 +112,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
     L.ta = take(8 * K * TA_MAX);
-    L.tsph = mode == MODE_DIST ? take(16 * TA_MAX) : o;
+    L.tsph = mode == MODE_DIST ? take(32 * TA_MAX) : o;
     L.ent = take(4 * lim.entries);
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
@@ -502,7 +502,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     bool poses_left = true, first_claim = true;
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
-    float e_abs = 0.0f, e_sph = 0.0f;
+    float e_abs = 0.0f, e_sph = 0.0f, rot_eps = 0.0f;
     // this lane's slab (lane mod K) of the pose's support-function transform
     const uint32_t my_k = lane % (uint32_t)K;
     const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
@@ -605,6 +605,23 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
             e_sph = 64.0f * 0x1p-24f *
                     (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
+            if (MODE == MODE_DIST) {
+                // how far the rotation's columns are from orthonormal (their
+                // Gram matrix minus the identity, largest entry, in FP64):
+                // the gaps along A's axes below allow for it
+                double dev = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+#pragma unroll
+                    for (int j = i; j < 3; j++) {
+                        double g = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 3; k++) g += (double)P.R[3 * k + i] * (double)P.R[3 * k + j];
+                        dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
+                    }
+                }
+                rot_eps = __double2float_ru(dev) + 0x1p-22f;
+            }
         }
 
         // ---- initial state ----
@@ -700,7 +717,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
                     float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
                     V3<float> cw = xform_f32(P, c);
-                    tsph[lane] = make_float4(cw.x, cw.y, cw.z, r);
+                    tsph[2 * lane] = make_float4(cw.x, cw.y, cw.z, r);
+                    tsph[2 * lane + 1] = make_float4(hx, hy, hz, hx + hy + hz);  // A-frame half extents
                 }
                 wave_sync();
                 // -------- child-pair tests, 64 per pass --------
@@ -742,13 +760,27 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                 g = fmaxf(g, gk);
                             }
                             // second lower bound: distance of the circumscribed spheres
-                            float4 sa = tsph[ia];
+                            float4 sa = tsph[2 * ia];
                             float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
                             float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
                             float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
                             float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
                             float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
-                            lb = fmaxf(g * (1.0f - 0x1p-20f), gs);
+                            // third lower bound: separating-axis gaps along A's own
+                            // axes (the rotation's columns), with A's record as a box in
+                            // its frame and B's as an axis-aligned box; the allowances
+                            // cover non-unit, non-orthogonal columns and FP32 rounding
+                            const float4 ea = tsph[2 * ia + 1];
+                            float ga = -INFINITY;
+#pragma unroll
+                            for (int i = 0; i < 3; i++) {
+                                const float c0 = P.R[i], c1 = P.R[3 + i], c2 = P.R[6 + i];
+                                const float p = __builtin_fmaf(c0, dx, __builtin_fmaf(c1, dy, c2 * dz));
+                                const float rbi = __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
+                                ga = fmaxf(ga, fabsf(p) - (i == 0 ? ea.x : i == 1 ? ea.y : ea.z) - rbi);
+                            }
+                            ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
+                            lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), ga);
                             survive = lb <= tau;
                         } else {
                             bool sep = false;
