@@ -715,7 +715,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     const float *b = rbnd + (size_t)(f_base + lane) * 2 * K;
                     V3<float> c = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
                     float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
-                    float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                    // the map stretches lengths by at most 1 + 1.5 rot_eps
+                    float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f + 2.0f * rot_eps);
                     V3<float> cw = xform_f32(P, c);
                     tsph[2 * lane] = make_float4(cw.x, cw.y, cw.z, r);
                     tsph[2 * lane + 1] = make_float4(hx, hy, hz, hx + hy + hz);  // A-frame half extents

@@ -280,3 +280,36 @@ def test_results_do_not_depend_on_batch_composition():
     again, _ = cb.collide(ma, mb, torch.from_numpy(P).to(DEV))
     assert np.array_equal(full.cpu().numpy()[::7], part.cpu().numpy())
     assert np.array_equal(full.cpu().numpy(), again.cpu().numpy())
+
+
+@pytest.mark.parametrize("bv", ["aabb", "dop18"])
+def test_non_rigid_pose_matrices_match_oracle(bv):
+    """The BV bounds allow for a pose matrix that is not a rotation (its
+    columns' Gram matrix is measured per pose), so distances and booleans
+    still match the oracle, which applies the matrix as given."""
+    _log(f"non-rigid poses bv={bv}")
+    rng = np.random.default_rng(5150)
+    (va, ta), (vb, tb) = W.meshes(0)
+    n = 96
+    R = poses.uniform_rotations(n, rng)
+    # stretch and shear: the columns are off orthonormal by up to about 4e-3
+    D = np.eye(3)[None] + rng.uniform(-2e-3, 2e-3, size=(n, 3, 3))
+    t = poses.shell_translations(n, 1.6, 3.0, rng)
+    P = poses.compose(R @ D, t)
+    kw = dict(bv=cb.AABB if bv == "aabb" else cb.DOP18, branching=4, leaf_size=1, bits=8)
+    ma, mb = cb.Model.build(va, ta, **kw).to(DEV), cb.Model.build(vb, tb, **kw).to(DEV)
+    Pd = torch.from_numpy(P).to(DEV)
+    d, st = cb.distance(ma, mb, Pd)
+    hit, hst = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT)
+    A, B = W.oracle_meshes(0)
+    cls = oracle.classify_batch(A, B, P, configs.WORKLOADS[0].margin(va, vb))
+    ref, _ = oracle.distance_batch(A, B, P)
+    sep, col = cls == oracle.SEPARATED, cls == oracle.COLLIDING
+    assert sep.sum() > 30 and col.sum() > 5
+    assert (st.cpu().numpy() == 0).all() and (hst.cpu().numpy() == 0).all()
+    got = d.cpu().numpy().astype(np.float64)
+    rel = np.abs(got[sep] - ref[sep]) / ref[sep]
+    assert rel.max() <= 1e-5, rel.max()
+    assert (got[col] == 0).all()
+    h = hit.cpu().numpy().astype(bool)
+    assert np.array_equal(h[sep | col], col[sep | col])
