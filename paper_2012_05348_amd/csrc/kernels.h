@@ -60,8 +60,9 @@ struct WsHeader {
     uint32_t q_head;      // next item slot to claim (8-byte aligned: read together with q_tail)
     uint32_t q_tail;      // next item slot to reserve
     uint32_t pad1[30];
-    uint32_t pending;     // poses + published items not yet finished
-    uint32_t pad2[31];
+    uint32_t pending;     // started waves that may still start poses + published items not yet finished
+    uint32_t gone;        // set once helpers began to leave: no unit hands work over after that
+    uint32_t pad2[30];
     uint32_t pad3[32];
 };
 static_assert(sizeof(WsHeader) == 512, "workspace header size");

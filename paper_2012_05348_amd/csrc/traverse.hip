@@ -450,7 +450,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     // ready.  Returns the number of items published (n, or 0 if the queue
     // is full; the slots reserved below its end are then published void).
     auto publish = [&](uint32_t pose, uint32_t n, uint32_t n_ent, float best) -> uint32_t {
-        uint32_t first = 0, ok = 0, sink = 0;
+        uint32_t first = 0, ok = 0, sink = 0, left = 0;
+        // once helpers have begun to leave, a claimed slot may have nobody
+        // behind it: publish nothing (this unit's own count in `pending`
+        // keeps any helper from leaving while it publishes)
+        if (lane == 0) left = rmw_read(&hdr->gone);
+        if (uni(left)) return 0u;
         if (lane == 0) {
             first = rmw_add(&hdr->q_tail, n);
             ok = first + n <= q.ws.item_cap && first + n >= first;
@@ -500,6 +505,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     };
 
     bool poses_left = true, first_claim = true;
+    // A wave with a pose to run counts as work that may still publish items
+    // until it finds the pose queue empty; a wave that starts late, after
+    // helpers left, therefore never waits on them and never hands work to
+    // them.  (The count is not waited for here: the wave's first memory
+    // waits complete it long before it could publish.)  A wave whose block
+    // index is past the poses gets none from the queue either: it holds no
+    // count and goes straight to helping or exits.
+    const bool counted = can_donate && blockIdx.x < q.n_poses;
+    if (counted && lane == 0) rmw_add(&hdr->pending, 1u);
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
     float e_abs = 0.0f, e_sph = 0.0f, rot_eps = 0.0f;
@@ -519,6 +533,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             uint32_t p = blockIdx.x;
             if (!first_claim && lane == 0) p = gridDim.x + atomicAdd(&hdr->pose_next, 1u);
             first_claim = false;
+            // (queue claims start at the grid size, past any block index)
             pose = uni(p);
             if (t_first == 0) t_first = wall_clock64();
             if (pose >= q.n_poses) {
@@ -526,7 +541,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 t_drain = wall_clock64();
                 // this wave starts no more poses: it no longer counts as work
                 // that could still publish items
-                if (can_donate && lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
+                if (counted && lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
             }
         }
         if (!poses_left) {
@@ -552,9 +567,21 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     got = 1;
                     break;
                 }
-                if (uni(pend) == 0) break;
+                if (uni(pend) == 0) {
+                    // nothing runs: stop all hand-over for good, then leave
+                    // unless some wave started meanwhile
+                    uint32_t again = 0;
+                    if (lane == 0) {
+                        rmw_xchg(&hdr->gone, 1u);
+                        again = rmw_read(&hdr->pending);
+                    }
+                    if (uni(again) == 0) break;
+                }
                 if (wall_clock64() - t0 > kWaitLimit) {
-                    if (lane == 0) rmw_xchg(&hdr->error, 1u);
+                    if (lane == 0) {
+                        rmw_xchg(&hdr->error, 1u);
+                        rmw_xchg(&hdr->gone, 1u);
+                    }
                     break;
                 }
                 if (spin < 4) __builtin_amdgcn_s_sleep(8);
@@ -1227,7 +1254,7 @@ __global__ void init_kernel(WsHeader *hdr, uint8_t *hit, uint8_t *status, unsign
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < sizeof(WsHeader) / 4) {
         uint32_t v = 0;
-        if (i == offsetof(WsHeader, pending) / 4) v = pending0;  // every wave holds work until it drains
+        if (i == offsetof(WsHeader, pending) / 4) v = pending0;  // waves add themselves when they start
         ((uint32_t *)hdr)[i] = v;
     }
     if (i < n_ready) ready[i] = 0;
@@ -1495,9 +1522,9 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     if (q.no_split && grid > q.n_poses) grid = q.n_poses;
     if (grid > kMaxWaves) grid = kMaxWaves;  // rows of per-wave counters in the workspace
     {
-        // workspace init: header (pending work = the waves, each until it
-        // finds the pose queue empty), per-pose outputs, and the item
-        // queue's ready flags (its slots are numbered from 0 in every query)
+        // workspace init: header (no pending work: each wave adds itself
+        // when it starts), per-pose outputs, and the item queue's ready
+        // flags (its slots are numbered from 0 in every query)
         const uint32_t n = q.n_poses;
         const bool dist = q.mode == MODE_DIST, pairs = q.mode == MODE_PAIRS;
         const uint32_t n_ready = q.no_split ? 0u : q.ws.item_cap;
@@ -1506,7 +1533,7 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
                            dist ? nullptr : q.hit, q.status, dist ? q.ws.best32 : nullptr,
                            dist ? q.ws.best64 : nullptr, pairs ? q.ws.pair_cnt : nullptr,
                            pairs ? q.ws.pair_cursor : nullptr, q.mode == MODE_BOOL ? q.ws.hitw : nullptr, q.ws.ready,
-                           n_ready, n, q.no_split ? 0u : grid);
+                           n_ready, n, 0u);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

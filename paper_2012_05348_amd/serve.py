@@ -139,6 +139,9 @@ class Server:
         (booleans and distances in request pose order) and throughput."""
         import torch
         R, N = len(req), len(req.poses)
+        if R and int(req.count.max()) > self.max_poses:
+            raise ValueError(f"a request of {int(req.count.max())} poses exceeds the {self.max_poses} poses one "
+                             "launch holds; raise launch_cap or memory_budget")
         # per kind: its requests in arrival order and their poses, contiguous
         kinds = {}
         for k in (COLLIDE, DISTANCE):

@@ -63,3 +63,10 @@ def test_results_are_the_same_alone_and_in_the_mix(server, realtime):
         else:
             assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), r
     assert (req.kind == serve.COLLIDE).any() and (req.kind == serve.DISTANCE).any()
+
+
+def test_a_request_larger_than_a_launch_is_rejected(server):
+    _, obs, srv = server
+    req = serve.make_requests(3, np.inf, len(obs), np.random.default_rng(3), batch_min=700, batch_max=800)
+    with pytest.raises(ValueError):
+        srv.run(req, realtime=False)
