@@ -296,9 +296,16 @@ def cpu_baseline(w, threads, budget_s=10.0):
         run(A, B, sample, threads=threads)
     dt = time.perf_counter() - t0
     progress(f"  oracle: {passes} pass(es) over {n_sample} poses in {dt:.2f} s")
+    # the same oracle on one thread, over a shorter sample (about budget_s / 4)
+    n1 = int(min(n, max(64, budget_s / 4 / max(per_pose * threads, 1e-9))))
+    t0 = time.perf_counter()
+    run(A, B, P[:n1], threads=1)
+    dt1 = time.perf_counter() - t0
+    progress(f"  oracle, one thread: {n1} poses in {dt1:.2f} s")
     return {"value": passes * n_sample / dt, "unit": "poses/s", "cores": threads, "kind": "oracle",
             "sample": f"{passes} pass(es) over the first {n_sample} of the {n} poses ({dt:.1f} s); "
-                      "FP64 Algorithm 1 on the oracle's own binary AABB tree, early exit per pose"}
+                      "FP64 Algorithm 1 on the oracle's own binary AABB tree, early exit per pose",
+            "single_thread": {"value": n1 / dt1, "unit": "poses/s", "sample": f"the first {n1} poses ({dt1:.1f} s)"}}
 
 
 def main():

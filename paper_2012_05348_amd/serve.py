@@ -116,7 +116,7 @@ class Server:
     """Continuous-batching request loop over a resident obstacle set."""
 
     def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
-                 memory_budget=2 << 30, max_poses=None, launch_cap=16384):
+                 memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None):
         self.link, self.obstacles, self.device = link, obstacles, device
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
@@ -132,16 +132,21 @@ class Server:
             # larger launches add latency and little throughput
             max_poses = min(lo, launch_cap)
         self.max_poses = max_poses
-        self.slots = [_Slot(link, k, max_poses, device) for k in (COLLIDE, DISTANCE) for _ in range(slots_per_kind)]
+        # distance launches cost far more per pose: a smaller cap keeps them
+        # short, so that requests behind them wait less
+        self.cap = {COLLIDE: max_poses, DISTANCE: min(max_poses, distance_cap or max_poses)}
+        self.slots = [_Slot(link, k, self.cap[k], device) for k in (COLLIDE, DISTANCE) for _ in range(slots_per_kind)]
 
     def run(self, req: Requests, realtime=True):
         """Serve every request; returns per-request latencies (s), per-pose results
         (booleans and distances in request pose order) and throughput."""
         import torch
         R, N = len(req), len(req.poses)
-        if R and int(req.count.max()) > self.max_poses:
-            raise ValueError(f"a request of {int(req.count.max())} poses exceeds the {self.max_poses} poses one "
-                             "launch holds; raise launch_cap or memory_budget")
+        for k in (COLLIDE, DISTANCE):
+            m = req.kind == k
+            if m.any() and int(req.count[m].max()) > self.cap[k]:
+                raise ValueError(f"a request of {int(req.count[m].max())} poses exceeds the {self.cap[k]} poses one "
+                                 "launch holds; raise launch_cap, distance_cap or memory_budget")
         # per kind: its requests in arrival order and their poses, contiguous
         kinds = {}
         for k in (COLLIDE, DISTANCE):
@@ -179,7 +184,7 @@ class Server:
                 arrived_t = now if realtime else np.inf
                 hi = lo
                 while hi < len(K["rs"]) and req.arrival[K["rs"][hi]] <= arrived_t and \
-                        K["pstart"][hi + 1] - K["pstart"][lo] <= self.max_poses:
+                        K["pstart"][hi + 1] - K["pstart"][lo] <= self.cap[s.kind]:
                     hi += 1
                 if hi == lo:
                     continue
