@@ -320,7 +320,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the query batch is sharded by poses across GPUs with no exchange "
-              "beyond gathering outputs, and this build runs on a single MI355X.", file=sys.stderr)
+              "beyond gathering outputs; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

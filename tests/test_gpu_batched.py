@@ -2,7 +2,7 @@
 uneven size in one launch (reduced size of the batched workload).
 
 The batched answers must equal the plain per-obstacle queries exactly (the
-plain kernel is the judge) and match the oracle on a sample of poses."""
+plain kernel is the reference) and match the oracle on a sample of poses."""
 import os
 import sys
 
