@@ -52,11 +52,28 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
+// DPP move with an identity for lanes that have no source (or sit in a row
+// the row mask leaves out): GFX9 controls row_shr:n = 0x110 + n,
+// row_bcast:15 = 0x142 (lane 15 of each row to the next row), row_bcast:31
+// = 0x143 (lane 31 to rows 2 and 3).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_or(uint32_t identity, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWS, 0xF, false);
+}
+// minimum over the wave (all lanes active): a min-scan inside each row of 16
+// lanes, then the row results carried across rows; lane 63 ends with the
+// wave's minimum.  All register-to-register (no LDS round trips).
 __device__ __forceinline__ float wave_min(float v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
+    const uint32_t inf = 0x7F800000u;
+    v = fminf(v, __uint_as_float(dpp_or<0x111, 0xF>(inf, __float_as_uint(v))));
+    v = fminf(v, __uint_as_float(dpp_or<0x112, 0xF>(inf, __float_as_uint(v))));
+    v = fminf(v, __uint_as_float(dpp_or<0x114, 0xF>(inf, __float_as_uint(v))));
+    v = fminf(v, __uint_as_float(dpp_or<0x118, 0xF>(inf, __float_as_uint(v))));
+    v = fminf(v, __uint_as_float(dpp_or<0x142, 0xA>(inf, __float_as_uint(v))));
+    v = fminf(v, __uint_as_float(dpp_or<0x143, 0xC>(inf, __float_as_uint(v))));
+    return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 63));
 }
 __device__ __forceinline__ double wave_min(double v)
 {
@@ -80,13 +97,16 @@ __device__ __forceinline__ uint32_t gather(uint32_t x, uint32_t src)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
 }
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
+// inclusive prefix sum over the wave (all lanes active), with DPP: a scan
+// inside each row of 16 lanes, then row totals carried to the later rows
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t)
 {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        uint32_t t = __shfl_up(v, o);
-        if (lane >= (uint32_t)o) v += t;
-    }
+    v += dpp_or<0x111, 0xF>(0u, v);
+    v += dpp_or<0x112, 0xF>(0u, v);
+    v += dpp_or<0x114, 0xF>(0u, v);
+    v += dpp_or<0x118, 0xF>(0u, v);
+    v += dpp_or<0x142, 0xA>(0u, v);
+    v += dpp_or<0x143, 0xC>(0u, v);
     return v;
 }
 
@@ -1132,14 +1152,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 const uint32_t slot = mbcnt(m_act);
                 meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
             }
-            {
-                uint32_t nbytes = 0;
-                if (act) nbytes = (topo_leaf(my_pA) ? 0u : topo_count(my_pA) * code_bytes_A) +
-                                  (topo_leaf(my_pB) ? 0u : topo_count(my_pB) * code_bytes_B);
-#pragma unroll
-                for (int o = 1; o < PMAX; o <<= 1) nbytes += __shfl_xor(nbytes, o);
-                cnt.node_bytes += lane_of(nbytes, 0);
-            }
             // decode: one lane per new record, A records first, then B records
             // (register staging: the new frame may overwrite the popped
             // entries' own records).  A record's entry is the popped lane whose
@@ -1162,6 +1174,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             uint32_t my_topo = 0;
             float my_b[2 * K];
             const bool dec = lane < total_rec;
+            {
+                // algorithmic bytes: topology word and codes of every decoded child
+                const bool from_node = dec && !topo_leaf(sideA ? g_pA : g_pB);
+                cnt.node_bytes += (unsigned long long)__popcll(__ballot(from_node && sideA)) * code_bytes_A +
+                                  (unsigned long long)__popcll(__ballot(from_node && !sideA)) * code_bytes_B;
+            }
             if (dec) {
                 const uint32_t c = r - off;
                 const uint32_t prec = sideA ? (g_e & REC_MASK) : ((g_e >> REC_BITS) & REC_MASK);
