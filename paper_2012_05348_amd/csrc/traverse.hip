@@ -75,12 +75,6 @@ __device__ __forceinline__ float wave_min(float v)
     v = fminf(v, __uint_as_float(dpp_or<0x143, 0xC>(inf, __float_as_uint(v))));
     return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 63));
 }
-__device__ __forceinline__ double wave_min(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
 // DPP row shifts (within each row of 16 lanes; 0 where there is no source lane)
 template <int N>
 __device__ __forceinline__ uint32_t row_shr(uint32_t v)
