@@ -124,7 +124,7 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 
 /* Per-pose status bytes written by the queries */
 #define CBVH_POSE_OK 0u
-#define CBVH_POSE_STACK_OVERFLOW 1u /* traversal state exhausted and no room to donate it; results invalid */
+#define CBVH_POSE_STACK_OVERFLOW 1u /* traversal state exhausted and nobody to hand it to; results invalid */
 #define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
 #define CBVH_POSE_FP64_OVERFLOW 3u  /* workspace buffer of leaf pairs for FP64 re-evaluation full; results invalid */
 #define CBVH_POSE_BAD_OBSTACLE 4u   /* batched queries: the pose's obstacle index is out of range; results invalid */
@@ -135,13 +135,16 @@ size_t cbvh_workspace_bytes(const cbvh_model *a, const cbvh_model *b, uint32_t n
                             uint32_t pair_capacity);
 
 /* How a query runs: one launch of persistent wavefronts.  Each takes poses
- * from a queue and traverses one pose at a time.  Once no pose is left, a
- * wavefront waits for work items: busy wavefronts hand the pending node
+ * from a queue and traverses one pose at a time.  Once no pose is left, some
+ * wavefronts wait for work items: busy wavefronts hand the pending node
  * pairs nearest their roots (with their decoded bounds) to waiting ones, and
  * a pose whose traversal state would overflow LDS hands over all of its
  * pending pairs.  Per-pose answers are merged in device memory, so results
- * do not depend on how the work was split.  The workspace holds the queue:
- * calls that share a workspace must not overlap in time.
+ * do not depend on how the work was split.  Waiting wavefronts leave once no
+ * started wavefront can hand over work any more; a wavefront that starts
+ * after that (possible when other launches hold the GPU) runs its poses
+ * alone.  The workspace holds the queue: calls that share a workspace must
+ * not overlap in time; calls on different workspaces may.
  *
  * Collision detection for a batch of poses (Algorithm 1; leaf test is the
  * closed triangle-triangle intersection, touching counts).
