@@ -126,7 +126,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
     L.ta = take(8 * K * TA_MAX);
-    L.tsph = mode == MODE_DIST ? take(32 * TA_MAX) : o;
+    L.tsph = take(32 * TA_MAX);
     L.ent = take(4 * lim.entries);
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
@@ -646,7 +646,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
             e_sph = 64.0f * 0x1p-24f *
                     (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
-            if (MODE == MODE_DIST) {
+            {
                 // how far the rotation's columns are from orthonormal (their
                 // Gram matrix minus the identity, largest entry, in FP64):
                 // the gaps along A's axes below allow for it
@@ -751,7 +751,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         }
                     }
                 }
-                if (MODE == MODE_DIST && lane < f_nA) {
+                if (lane < f_nA) {
                     // circumscribed sphere of the record's box, centre moved by the pose
                     const float *b = rbnd + (size_t)(f_base + lane) * 2 * K;
                     V3<float> c = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
@@ -832,6 +832,28 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                 sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
                                 if (MODE == MODE_BOOL)
                                     ov = fminf(ov, fminf(tA[2 * k + 1], bB[2 * k + 1]) - fmaxf(tA[2 * k], bB[2 * k]));
+                            }
+                            {
+                                // separating axes along A's own axes (the rotation's
+                                // columns): A's record as a box in its frame, B's as an
+                                // axis-aligned box; separated only beyond the allowances
+                                // for non-orthonormal columns and FP32 rounding
+                                const float4 sa = tsph[2 * ia], ea = tsph[2 * ia + 1];
+                                const float dx = 0.5f * (bB[0] + bB[1]) - sa.x, dy = 0.5f * (bB[2] + bB[3]) - sa.y,
+                                            dz = 0.5f * (bB[4] + bB[5]) - sa.z;
+                                const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]),
+                                            hz = 0.5f * (bB[5] - bB[4]);
+                                float ga = -INFINITY;
+#pragma unroll
+                                for (int i = 0; i < 3; i++) {
+                                    const float c0 = P.R[i], c1 = P.R[3 + i], c2 = P.R[6 + i];
+                                    const float p = __builtin_fmaf(c0, dx, __builtin_fmaf(c1, dy, c2 * dz));
+                                    const float rbi =
+                                        __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
+                                    ga = fmaxf(ga, fabsf(p) - (i == 0 ? ea.x : i == 1 ? ea.y : ea.z) - rbi);
+                                }
+                                ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
+                                sep |= ga > 0.0f;
                             }
                             survive = !sep;
                             // early exit: the most deeply overlapping pair is expanded first
