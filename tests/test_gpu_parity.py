@@ -313,3 +313,46 @@ def test_non_rigid_pose_matrices_match_oracle(bv):
     assert (got[col] == 0).all()
     h = hit.cpu().numpy().astype(bool)
     assert np.array_equal(h[sep | col], col[sep | col])
+
+
+@pytest.mark.parametrize("bits", [8, 0])
+def test_coincident_and_degenerate_geometry_match_oracle(bits):
+    """Degenerate inputs the method has to decide exactly: a model against
+    itself at the identity pose (every triangle coincides with itself and
+    touches its neighbours along shared edges and vertices: coplanar and
+    touching pairs, all decided by the FP64 stage), and a mesh with
+    zero-area triangles.  Pair lists, booleans and distances equal the
+    oracle's."""
+    _log(f"coincident geometry bits={bits}")
+    (va, ta), _ = W.meshes(0)
+    m = cb.Model.build(va, ta, bv=cb.AABB, branching=4, leaf_size=1, bits=bits).to(DEV)
+    A = oracle.Mesh(va, ta)
+    P = np.eye(3, 4, dtype=np.float32)[None]
+    Pd = torch.from_numpy(P).to(DEV)
+    cap = 1 << 16
+    hit, st, pairs, offs = cb.collide(m, m, Pd, flags=cb.PAIRS, pair_capacity=cap)
+    assert st.cpu().numpy()[0] == 0 and hit.cpu().numpy()[0] == 1
+    got = pairs.cpu().numpy()[: offs.cpu().numpy()[1], 1:].astype(np.uint32)
+    ref = oracle.collide_pairs(A, A, P[0])
+    assert len(ref) > len(ta)  # every triangle with itself, plus its neighbours
+    assert np.array_equal(got, ref)
+    d, dst = cb.distance(m, m, Pd)
+    assert dst.cpu().numpy()[0] == 0 and d.cpu().numpy()[0] == 0.0
+    # zero-area triangles (a collapsed vertex and a collapsed edge) among ordinary ones
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0], [1, 1, 0], [0.5, 0.5, 0.5]], np.float32)
+    T = np.array([[0, 1, 2], [1, 3, 2], [3, 4, 1], [0, 5, 5], [2, 5, 1]], np.uint32)
+    md = cb.Model.build(V, T, bv=cb.AABB, branching=4, leaf_size=1, bits=bits).to(DEV)
+    D = oracle.Mesh(V, T)
+    rng = np.random.default_rng(99)
+    Q = poses.compose(poses.uniform_rotations(64, rng), poses.shell_translations(64, 0.0, 1.5, rng))
+    Qd = torch.from_numpy(Q).to(DEV)
+    hit, st, pairs, offs = cb.collide(md, md, Qd, flags=cb.PAIRS, pair_capacity=cap)
+    d, dst = cb.distance(md, md, Qd)
+    st, pairs, offs, d = st.cpu().numpy(), pairs.cpu().numpy(), offs.cpu().numpy(), d.cpu().numpy()
+    assert (st == 0).all() and (dst.cpu().numpy() == 0).all()
+    ref_d, _ = oracle.distance_batch(D, D, Q)
+    for i, q in enumerate(Q):
+        assert np.array_equal(pairs[offs[i]:offs[i + 1], 1:].astype(np.uint32), oracle.collide_pairs(D, D, q)), i
+    pos = ref_d > 0
+    assert (d[~pos] == 0).all()
+    assert (np.abs(d[pos] - ref_d[pos]) / ref_d[pos]).max() <= 1e-5
