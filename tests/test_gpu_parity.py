@@ -356,3 +356,29 @@ def test_coincident_and_degenerate_geometry_match_oracle(bits):
     pos = ref_d > 0
     assert (d[~pos] == 0).all()
     assert (np.abs(d[pos] - ref_d[pos]) / ref_d[pos]).max() <= 1e-5
+
+
+def test_large_batch_keeps_every_pose_within_capacity():
+    """A batch of 262,144 poses in one launch (sixteen times the scaled
+    workload's): no pose overflows a queue or buffer, compressed and FP32
+    descriptors agree on every pose, and a margin-filtered sample matches the
+    oracle."""
+    n = 1 << 18
+    rng = np.random.default_rng(262144)
+    P = poses.compose(poses.uniform_rotations(n, rng), poses.box_translations(n, 2.5, rng))
+    Pd = torch.from_numpy(P).to(DEV)
+    _log(f"large batch n={n}")
+    out = {}
+    for compressed in (True, False):
+        ma, mb = models(0, compressed)
+        hit, st = cb.collide(ma, mb, Pd, flags=cb.EARLY_EXIT)
+        out[compressed] = (hit.cpu().numpy().astype(bool), st.cpu().numpy())
+        assert (out[compressed][1] == 0).all()
+    assert np.array_equal(out[True][0], out[False][0])
+    (va, ta), (vb, tb) = W.meshes(0)
+    A, B = W.oracle_meshes(0)
+    idx = W.sample_indices(n, 256, seed=5)
+    cls = oracle.classify_batch(A, B, P[idx], configs.WORKLOADS[0].margin(va, vb))
+    ok = cls != oracle.MARGINAL
+    assert ok.sum() > 200
+    assert np.array_equal(out[True][0][idx][ok], cls[ok] == oracle.COLLIDING)
