@@ -115,6 +115,7 @@ struct QueryArgs {
     uint32_t donate_keep;       // entries a donor keeps at least (0 = half of its stack)
     uint32_t donate_min_top;    // a unit feeds waiting waves only with at least this many entries
     uint32_t max_donate;        // entries one look at the item queue may hand over
+    uint32_t prio_steps;        // a unit's issue priority rises by one every this many steps (0: never)
     Workspace ws;
 };
 
