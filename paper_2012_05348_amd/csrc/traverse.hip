@@ -759,7 +759,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         }
                     }
                 }
-                if (lane < f_nA) {
+                if ((MODE == MODE_DIST || K == 3) && lane < f_nA) {
                     // circumscribed sphere of the record's box, centre moved by the pose
                     const float *b = rbnd + (size_t)(f_base + lane) * 2 * K;
                     V3<float> c = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
@@ -841,11 +841,14 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                 if (MODE == MODE_BOOL)
                                     ov = fminf(ov, fminf(tA[2 * k + 1], bB[2 * k + 1]) - fmaxf(tA[2 * k], bB[2 * k]));
                             }
-                            {
+                            if constexpr (K == 3) {
                                 // separating axes along A's own axes (the rotation's
                                 // columns): A's record as a box in its frame, B's as an
                                 // axis-aligned box; separated only beyond the allowances
-                                // for non-orthonormal columns and FP32 rounding
+                                // for non-orthonormal columns and FP32 rounding (AABB
+                                // models only: an 18-DOP's diagonal slabs already cut
+                                // what these axes would, and the test costs more than
+                                // it saves there)
                                 const float4 sa = tsph[2 * ia], ea = tsph[2 * ia + 1];
                                 const float dx = 0.5f * (bB[0] + bB[1]) - sa.x, dy = 0.5f * (bB[2] + bB[3]) - sa.y,
                                             dz = 0.5f * (bB[4] + bB[5]) - sa.z;
