@@ -382,3 +382,46 @@ def test_large_batch_keeps_every_pose_within_capacity():
     ok = cls != oracle.MARGINAL
     assert ok.sum() > 200
     assert np.array_equal(out[True][0][idx][ok], cls[ok] == oracle.COLLIDING)
+
+
+def test_concurrent_launches_on_several_streams_neither_wait_nor_change_answers():
+    """Four queries in flight at once on four streams (two distance, two
+    collision launches, each sized to fill the GPU on its own), so a launch's
+    waves cannot all be resident: waiting waves must not wait on waves that
+    have not started (no wait-limit timeouts), and every answer equals the
+    same query run alone."""
+    wd, wc = configs.WORKLOADS[2], configs.WORKLOADS[1]
+    Pd_ = torch.from_numpy(wd.raw_poses()).to(DEV)
+    Pc_ = torch.from_numpy(wc.raw_poses()).to(DEV)
+    md, mc = models(2), models(1)
+    ref_d, _ = cb.distance(*md, Pd_)
+    ref_c, _ = cb.collide(*mc, Pc_)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    jobs = []
+    for i, s in enumerate(streams):
+        kind = "dist" if i % 2 == 0 else "coll"
+        m, P = (md, Pd_) if kind == "dist" else (mc, Pc_)
+        n = P.shape[0]
+        ws = cb.workspace(m[0], m[1], n, 0 if kind == "dist" else cb.EARLY_EXIT, 0, DEV)
+        out = torch.empty(n, dtype=torch.float32 if kind == "dist" else torch.uint8, device=DEV)
+        st = torch.empty(n, dtype=torch.uint8, device=DEV)
+        jobs.append((kind, s, m, P, n, ws, out, st))
+    import time
+    t0 = time.perf_counter()
+    for kind, s, m, P, n, ws, out, st in jobs:
+        if kind == "dist":
+            cb.cbvh_distance(m[0].handle, m[0].dev, m[1].handle, m[1].dev, P, n, 0, out, st, ws.buf, stream=s)
+        else:
+            cb.cbvh_collide(m[0].handle, m[0].dev, m[1].handle, m[1].dev, P, n, cb.EARLY_EXIT, out, None, 0, None,
+                            st, ws.buf, stream=s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _log(f"concurrent launches: {dt * 1e3:.1f} ms")
+    assert dt < 2.0
+    for kind, s, m, P, n, ws, out, st in jobs:
+        stats = cb.cbvh_stats(ws.buf)
+        assert stats["wait_timeouts"] == 0
+        assert (st.cpu().numpy() == 0).all()
+        ref = ref_d if kind == "dist" else ref_c
+        assert torch.equal(out.cpu(), ref.cpu())
