@@ -408,6 +408,8 @@ constexpr uint32_t kSyncPeriod = 4;
 constexpr uint32_t kMaxDonate = 32;
 // a unit hands work over only while it holds at least this many entries
 constexpr uint32_t kDonateMinTop = 2;
+// steps after which a collision unit looks at the item queue every other step
+constexpr uint32_t kOldSteps = 48;
 // pose word of a queue slot that holds no work
 constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 
@@ -1067,7 +1069,10 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
 
             // -------- feed waiting waves with the bottom of the stack --------
             if (can_donate && top >= q.donate_min_top && steps >= next_look && steps >= q.donate_min_steps) {
-                next_look = steps + q.donate_period;
+                // collision queries: a unit that has run long looks every other
+                // step, so the long units (the batch's critical path) win the
+                // waiting helpers more often (distance queries lose by it)
+                next_look = steps + ((MODE != MODE_DIST && steps >= kOldSteps) ? 2u : q.donate_period);
                 uint32_t want = 0;
                 if (lane == 0) {
                     unsigned long long ht = poll64((unsigned long long *)&hdr->q_head);
