@@ -272,6 +272,47 @@ def run_serving(cb, dev, n_requests=1500):
     return out
 
 
+def run_large_obstacle_set(cb, dev, n_obstacles=192, n_poses=32768, calls=9):
+    """Descriptor formats on a working set beyond the Infinity Cache: one
+    20k-triangle link against n_obstacles separate device copies of a
+    200k-triangle 18-DOP obstacle (about 11 MB each with triangles), poses
+    spread uniformly over them; kernel time per format, answers compared."""
+    import torch
+    from synth import meshes, poses
+    rng = np.random.default_rng(4242)
+    obs_mesh = meshes.torus(*meshes.torus_grid_for(200000), 1.0, 0.3, 0.02, rng)
+    link_mesh = meshes.torus(*meshes.torus_grid_for(20000), 1.0, 0.3, 0.02, rng)
+    P = poses.compose(poses.uniform_rotations(n_poses, rng), poses.box_translations(n_poses, 1.5, rng))
+    obj = rng.integers(0, n_obstacles, n_poses).astype(np.uint32)
+    Pd, od = torch.from_numpy(P).to(dev), torch.from_numpy(obj).to(dev)
+    out, ref = {"obstacles": n_obstacles, "poses": n_poses}, None
+    for bits, key in ((16, "codes16"), (cb.BITS_FP16, "fp16"), (0, "fp32")):
+        progress(f"large obstacle set: {n_obstacles} copies, {key}")
+        kw = dict(bv=cb.DOP18, branching=8, leaf_size=4, bits=bits)
+        link = cb.Model.build(*link_mesh, **kw).to(dev)
+        base = cb.Model.build(*obs_mesh, **kw)
+        blob = base.blob()
+        obs = [cb.Model.load(blob).to(dev) for _ in range(n_obstacles)]
+        oset = cb.Obstacles(obs, dev)
+        ws = cb.workspace(link, link, n_poses, cb.EARLY_EXIT, 0, dev)
+        hit = torch.empty(n_poses, dtype=torch.uint8, device=dev)
+        st = torch.empty(n_poses, dtype=torch.uint8, device=dev)
+
+        def step():
+            cb.cbvh_collide_batch(link.handle, link.dev, oset.handle, Pd, od, n_poses, cb.EARLY_EXIT, hit, st, ws.buf)
+
+        traversal_kernel_ms(cb, step, ws.buf, 2)
+        k = traversal_kernel_ms(cb, step, ws.buf, calls)
+        h = hit.cpu().numpy()
+        ref = h if ref is None else ref
+        out[key] = {"descriptor_bytes_total": base.info()["descriptor_bytes"] * n_obstacles,
+                    "kernel_ms_median": float(np.median(k)), "kernel_ms_min": float(np.min(k)),
+                    "hits_equal": bool(np.array_equal(h, ref)), "status_ok": bool((st == 0).all().item())}
+        del link, obs, oset, ws, base
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, threads, budget_s=10.0):
     """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
     host: repeated passes over the workload's poses until about budget_s
@@ -315,6 +356,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true", help="skip the uncompressed twin and the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--large-obstacle-set", type=int, default=0, metavar="N",
+                    help="also time the descriptor formats on N device copies of a 200k-triangle obstacle")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -396,6 +439,8 @@ def main():
             out[key] = summarize(pr, 5)
         out["batched"] = run_batched(cb, dev, 10, 2)
         out["serving"] = run_serving(cb, dev)
+    if args.large_obstacle_set:
+        out["large_obstacle_set"] = run_large_obstacle_set(cb, dev, args.large_obstacle_set)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, threads=min(16, os.cpu_count() or 1))
     if args.calibrate_copy_mib:
