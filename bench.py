@@ -28,6 +28,9 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2012_05348_amd/csrc/traverse.hip", "paper_2012_05348_amd/csrc/geom.h",
                   "paper_2012_05348_amd/csrc/format.h", "paper_2012_05348_amd/csrc/kernels.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_dop18_16bit_torus100k.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_collide_dop18_16bit_torus100k.json")
+# VALU issue capacity: one wave64 FP32 VALU instruction per 4 cycles per SIMD, 1,024 SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
 def kernel_hash():
@@ -385,6 +388,15 @@ def main():
             tr = json.load(f)
         if tr.get("kernel_hash") == kernel_hash():
             traffic = tr.get("hbm_bytes_per_launch")
+    # the secondary ceiling, VALU issue, from the committed SQ counters of the same kernel source
+    valu = None
+    if os.path.exists(COUNTERS_FILE):
+        with open(COUNTERS_FILE) as f:
+            ct = json.load(f)
+        if ct.get("kernel_hash") == kernel_hash():
+            rate = ct["valu_insts_per_dispatch"] / (kavg_ms * 1e-3)
+            valu = {"insts_per_launch": ct["valu_insts_per_dispatch"], "achieved_per_s": rate,
+                    "peak_per_s": VALU_ISSUE_PEAK, "frac": rate / VALU_ISSUE_PEAK}
 
     out = {
         "metric": METRIC,
@@ -411,6 +423,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "kernel": "traverse_kernel<9,16,bool>", "kernel_avg_ms": kavg_ms,
             "call_avg_ms": float(np.mean(main_r["dev_ms"])), "algorithmic_bytes_per_launch": algo_bytes,
+            "valu_issue": valu,
         },
     }
     if not args.no_extra:
