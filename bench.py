@@ -318,8 +318,9 @@ def run_large_obstacle_set(cb, dev, n_obstacles=192, n_poses=32768, calls=9):
 
 def cpu_baseline(w, threads, budget_s=10.0):
     """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
-    host: repeated passes over the workload's poses until about budget_s
-    seconds of work have run (at most 8 passes; one pass for slow workloads)."""
+    host: repeated passes over the workload's poses until at least budget_s
+    seconds of work have run (at most 512 passes; for a slow workload one pass
+    over a prefix sized to the budget)."""
     import oracle
     progress("cpu baseline (oracle)")
     (va, ta), (vb, tb) = w.meshes()
@@ -333,12 +334,15 @@ def cpu_baseline(w, threads, budget_s=10.0):
     run(A, B, probe, threads=threads)
     per_pose = (time.perf_counter() - t0) / len(probe)
     n_sample = int(min(n, max(256, budget_s / max(per_pose, 1e-9))))
-    passes = 1 if n_sample < n else int(max(1, min(64, budget_s / max(per_pose * n, 1e-9))))
     sample = P[:n_sample]
+    passes = 0
     t0 = time.perf_counter()
-    for _ in range(passes):
+    while True:
         run(A, B, sample, threads=threads)
-    dt = time.perf_counter() - t0
+        passes += 1
+        dt = time.perf_counter() - t0
+        if n_sample < n or dt >= budget_s or passes >= 512:
+            break
     progress(f"  oracle: {passes} pass(es) over {n_sample} poses in {dt:.2f} s")
     # the same oracle on one thread, over a shorter sample (about budget_s / 4)
     n1 = int(min(n, max(64, budget_s / 4 / max(per_pose * threads, 1e-9))))
