@@ -98,9 +98,10 @@ def make_requests(n_requests, rate, n_obstacles, rng, batch_min=1, batch_max=409
 
 
 class _Slot:
-    def __init__(self, link, kind, max_poses, device):
+    def __init__(self, link, kind, max_poses, device, small_max):
         import torch
         self.kind = kind
+        self.small_max = small_max  # admits only requests of at most this many poses (None: any)
         self.stream = torch.cuda.Stream(device=device)
         self.P = torch.empty((max_poses, 3, 4), dtype=torch.float32, device=device)
         self.obj = torch.empty(max_poses, dtype=torch.int32, device=device)
@@ -108,15 +109,25 @@ class _Slot:
         self.status = torch.empty(max_poses, dtype=torch.uint8, device=device)
         self.ws = _aligned_empty(cbvh_workspace_bytes(link.handle, link.handle, max_poses,
                                                       EARLY_EXIT if kind == COLLIDE else 0, 0), device)
+        # pinned staging: the admitted requests' poses gathered in launch order, results back
+        self.hP = torch.empty((max_poses, 3, 4), dtype=torch.float32).pin_memory()
+        self.hobj = torch.empty(max_poses, dtype=torch.int32).pin_memory()
+        self.hout = torch.empty(max_poses, dtype=self.out.dtype).pin_memory()
+        self.hstatus = torch.empty(max_poses, dtype=torch.uint8).pin_memory()
         self.event = torch.cuda.Event()
-        self.busy = None  # (request range lo, hi, pose range lo, hi) while a launch is in flight
+        self.busy = None  # [(request, first pose in the launch, count)] while a launch is in flight
 
 
 class Server:
-    """Continuous-batching request loop over a resident obstacle set."""
+    """Continuous-batching request loop over a resident obstacle set.
+
+    Each query kind has `slots_per_kind` launch slots.  With two or more, the
+    first slot of a kind only admits small requests (at most `small_max`
+    poses), so that they never wait behind a launch that carries a request of
+    thousands of poses; the other slots admit any request, in arrival order."""
 
     def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
-                 memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None):
+                 memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None, small_max=256):
         self.link, self.obstacles, self.device = link, obstacles, device
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
@@ -135,7 +146,11 @@ class Server:
         # distance launches cost far more per pose: a smaller cap keeps them
         # short, so that requests behind them wait less
         self.cap = {COLLIDE: max_poses, DISTANCE: min(max_poses, distance_cap or max_poses)}
-        self.slots = [_Slot(link, k, self.cap[k], device) for k in (COLLIDE, DISTANCE) for _ in range(slots_per_kind)]
+        self.slots = []
+        for k in (COLLIDE, DISTANCE):
+            for i in range(slots_per_kind):
+                small = small_max if (slots_per_kind > 1 and i == 0 and small_max) else None
+                self.slots.append(_Slot(link, k, self.cap[k], device, small))
 
     def run(self, req: Requests, realtime=True):
         """Serve every request; returns per-request latencies (s), per-pose results
@@ -147,18 +162,13 @@ class Server:
             if m.any() and int(req.count[m].max()) > self.cap[k]:
                 raise ValueError(f"a request of {int(req.count[m].max())} poses exceeds the {self.cap[k]} poses one "
                                  "launch holds; raise launch_cap, distance_cap or memory_budget")
-        # per kind: its requests in arrival order and their poses, contiguous
-        kinds = {}
-        for k in (COLLIDE, DISTANCE):
-            rs = np.nonzero(req.kind == k)[0]
-            pidx = np.concatenate([np.arange(req.first[r], req.first[r] + req.count[r]) for r in rs]) if len(rs) \
-                else np.zeros(0, dtype=np.int64)
-            pstart = np.concatenate([[0], np.cumsum(req.count[rs])]).astype(np.int64)
-            P = torch.from_numpy(np.ascontiguousarray(req.poses[pidx])).pin_memory()
-            obj = torch.from_numpy(np.repeat(req.obstacle[rs], req.count[rs]).astype(np.int32)).pin_memory()
-            out = torch.empty(len(pidx), dtype=torch.uint8 if k == COLLIDE else torch.float32).pin_memory()
-            status = torch.empty(len(pidx), dtype=torch.uint8).pin_memory()
-            kinds[k] = dict(rs=rs, pidx=pidx, pstart=pstart, P=P, obj=obj, out=out, status=status, next=0)
+        hit = np.zeros(N, dtype=np.uint8)
+        dist = np.full(N, np.nan, dtype=np.float32)
+        status = np.zeros(N, dtype=np.uint8)
+        # per kind: its requests in arrival order, which are admitted, and the first not yet admitted
+        queue = {k: {"rs": np.nonzero(req.kind == k)[0], "admitted": None, "head": 0} for k in (COLLIDE, DISTANCE)}
+        for Q in queue.values():
+            Q["admitted"] = np.zeros(len(Q["rs"]), dtype=bool)
         done_at = np.full(R, np.nan)
         n_launch = 0
         max_batch = 0
@@ -169,41 +179,57 @@ class Server:
             progressed = False
             for s in self.slots:
                 if s.busy is not None and s.event.query():
-                    lo, hi, _, _ = s.busy
-                    done_at[kinds[s.kind]["rs"][lo:hi]] = time.perf_counter() - t0
-                    remaining -= hi - lo
+                    t_done = time.perf_counter() - t0
+                    out_np, st_np = s.hout.numpy(), s.hstatus.numpy()
+                    for r, off, c in s.busy:
+                        sl = slice(req.first[r], req.first[r] + c)
+                        (hit if s.kind == COLLIDE else dist)[sl] = out_np[off:off + c]
+                        status[sl] = st_np[off:off + c]
+                        done_at[r] = t_done
+                    remaining -= len(s.busy)
                     s.busy = None
                     progressed = True
                 if s.busy is not None:
                     continue
-                K = kinds[s.kind]
-                lo = K["next"]
-                if lo >= len(K["rs"]):
-                    continue
-                # admit every arrived request that fits this slot
+                Q = queue[s.kind]
+                rs, adm = Q["rs"], Q["admitted"]
+                while Q["head"] < len(rs) and adm[Q["head"]]:
+                    Q["head"] += 1
+                # admit arrived requests in arrival order while they fit (a
+                # small-request slot passes over the large ones)
                 arrived_t = now if realtime else np.inf
-                hi = lo
-                while hi < len(K["rs"]) and req.arrival[K["rs"][hi]] <= arrived_t and \
-                        K["pstart"][hi + 1] - K["pstart"][lo] <= self.cap[s.kind]:
-                    hi += 1
-                if hi == lo:
+                chosen, n = [], 0
+                for i in range(Q["head"], len(rs)):
+                    r = rs[i]
+                    if req.arrival[r] > arrived_t:
+                        break
+                    c = int(req.count[r])
+                    if adm[i] or (s.small_max is not None and c > s.small_max):
+                        continue
+                    if n + c > self.cap[s.kind]:
+                        break
+                    chosen.append((i, r, n, c))
+                    n += c
+                if not chosen:
                     continue
-                p0, p1 = int(K["pstart"][lo]), int(K["pstart"][hi])
-                n = p1 - p0
+                hP, hobj = s.hP.numpy(), s.hobj.numpy()
+                for i, r, off, c in chosen:
+                    hP[off:off + c] = req.poses[req.first[r]:req.first[r] + c]
+                    hobj[off:off + c] = req.obstacle[r]
+                    adm[i] = True
                 with torch.cuda.stream(s.stream):
-                    s.P[:n].copy_(K["P"][p0:p1], non_blocking=True)
-                    s.obj[:n].copy_(K["obj"][p0:p1], non_blocking=True)
+                    s.P[:n].copy_(s.hP[:n], non_blocking=True)
+                    s.obj[:n].copy_(s.hobj[:n], non_blocking=True)
                     if s.kind == COLLIDE:
                         cbvh_collide_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n,
                                            EARLY_EXIT, s.out, s.status, s.ws, stream=s.stream)
                     else:
                         cbvh_distance_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n, 0,
                                             s.out, s.status, s.ws, stream=s.stream)
-                    K["out"][p0:p1].copy_(s.out[:n], non_blocking=True)
-                    K["status"][p0:p1].copy_(s.status[:n], non_blocking=True)
+                    s.hout[:n].copy_(s.out[:n], non_blocking=True)
+                    s.hstatus[:n].copy_(s.status[:n], non_blocking=True)
                     s.event.record(s.stream)
-                s.busy = (lo, hi, p0, p1)
-                K["next"] = hi
+                s.busy = [(r, off, c) for _, r, off, c in chosen]
                 n_launch += 1
                 max_batch = max(max_batch, n)
                 progressed = True
@@ -211,12 +237,6 @@ class Server:
                 time.sleep(20e-6)
         makespan = time.perf_counter() - t0
         torch.cuda.synchronize()
-        hit = np.zeros(N, dtype=np.uint8)
-        dist = np.full(N, np.nan, dtype=np.float32)
-        status = np.zeros(N, dtype=np.uint8)
-        for k, K in kinds.items():
-            (hit if k == COLLIDE else dist)[K["pidx"]] = K["out"].numpy()
-            status[K["pidx"]] = K["status"].numpy()
         lat = done_at - req.arrival
         return {"latency_s": lat, "hit": hit, "dist": dist, "status": status, "makespan_s": makespan,
                 "poses_per_sec": N / makespan, "requests_per_sec": R / makespan, "launches": n_launch,
