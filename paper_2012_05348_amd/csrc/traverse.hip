@@ -11,7 +11,7 @@
 //   leafq    pending leaf pairs (two leaf topology words);
 //   ta       A's records of the current frame moved into B's frame.
 //
-// Node step: pop up to 4 entries whose child-pair tests fit in 64 lanes,
+// Node step: pop up to 8 entries whose child-pair tests fit in 64 lanes,
 // decode the children (one lane per child) into a new frame, transform A's
 // children with the pose's support-function coefficients, test every child
 // pair in its own lane (Algorithm 1's "a_i and b_j intersect", or a BV
@@ -350,6 +350,49 @@ __device__ __forceinline__ float dist_err_abs(const float *pose, float maxA, flo
     return 256.0f * 0x1p-24f * (tnorm + 3.5f * (maxA + maxB));
 }
 
+// Lower bound on the distance between A's box placed by the pose and B's
+// axis-aligned box: their gap along one direction n, from a point of A's
+// placed box to the point of B's box nearest to it (one round of alternating
+// projections started at A's centre).  For separated boxes this is close to
+// their true distance, where gaps along fixed axes can fall short by up to a
+// factor sqrt(3).  A's extent along n is its support function through the
+// pose's matrix, which holds for any matrix, so the allowance `e` covers FP32
+// rounding only.  Inputs: R the matrix (row-major), c A's centre placed by the
+// pose, ea A's half extents in its own frame, b B's x, y, z slabs (lo, hi),
+// d = c - B's centre, h B's half extents.  Returns -inf when the chosen
+// point lies in B's box (the boxes overlap).
+__device__ __forceinline__ float dir_gap(const float *R, float4 c, float4 ea, const float *b, float dx, float dy,
+                                         float dz, float hx, float hy, float hz, float e)
+{
+    // B's point nearest to A's centre, as an offset from it, taken into A's
+    // frame by the matrix's transpose and clamped to A's box
+    const float ox = __builtin_amdgcn_fmed3f(c.x, b[0], b[1]) - c.x;
+    const float oy = __builtin_amdgcn_fmed3f(c.y, b[2], b[3]) - c.y;
+    const float oz = __builtin_amdgcn_fmed3f(c.z, b[4], b[5]) - c.z;
+    const float u0 = __builtin_amdgcn_fmed3f(__builtin_fmaf(R[0], ox, __builtin_fmaf(R[3], oy, R[6] * oz)), -ea.x, ea.x);
+    const float u1 = __builtin_amdgcn_fmed3f(__builtin_fmaf(R[1], ox, __builtin_fmaf(R[4], oy, R[7] * oz)), -ea.y, ea.y);
+    const float u2 = __builtin_amdgcn_fmed3f(__builtin_fmaf(R[2], ox, __builtin_fmaf(R[5], oy, R[8] * oz)), -ea.z, ea.z);
+    // that point of A's placed box, and n towards B's point nearest to it
+    const float px = __builtin_fmaf(R[0], u0, __builtin_fmaf(R[1], u1, __builtin_fmaf(R[2], u2, c.x)));
+    const float py = __builtin_fmaf(R[3], u0, __builtin_fmaf(R[4], u1, __builtin_fmaf(R[5], u2, c.y)));
+    const float pz = __builtin_fmaf(R[6], u0, __builtin_fmaf(R[7], u1, __builtin_fmaf(R[8], u2, c.z)));
+    const float nx = __builtin_amdgcn_fmed3f(px, b[0], b[1]) - px;
+    const float ny = __builtin_amdgcn_fmed3f(py, b[2], b[3]) - py;
+    const float nz = __builtin_amdgcn_fmed3f(pz, b[4], b[5]) - pz;
+    // min over B of n.y minus max over placed A of n.x
+    const float m0 = __builtin_fmaf(R[0], nx, __builtin_fmaf(R[3], ny, R[6] * nz));
+    const float m1 = __builtin_fmaf(R[1], nx, __builtin_fmaf(R[4], ny, R[7] * nz));
+    const float m2 = __builtin_fmaf(R[2], nx, __builtin_fmaf(R[5], ny, R[8] * nz));
+    const float ext = __builtin_fmaf(
+        ea.x, fabsf(m0),
+        __builtin_fmaf(ea.y, fabsf(m1),
+                       __builtin_fmaf(ea.z, fabsf(m2),
+                                      __builtin_fmaf(hx, fabsf(nx), __builtin_fmaf(hy, fabsf(ny), hz * fabsf(nz))))));
+    const float gap = -__builtin_fmaf(nx, dx, __builtin_fmaf(ny, dy, nz * dz)) - ext;
+    const float nn = __builtin_fmaf(nx, nx, __builtin_fmaf(ny, ny, nz * nz));
+    return nn > 0x1p-100f ? gap * __builtin_amdgcn_rsqf(nn) * (1.0f - 0x1p-20f) - e : -INFINITY;
+}
+
 // 16-bit reciprocal for n in [1, 8]: (x * r) >> 16 == x / n for x < 64
 __device__ __forceinline__ uint32_t recip16(uint32_t n) { return (65536u + n - 1u) / n; }
 
@@ -532,7 +575,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     if (counted && lane == 0) rmw_add(&hdr->pending, 1u);
     uint32_t cur_pose = 0xFFFFFFFFu;
     Pose P;
-    float e_abs = 0.0f, e_sph = 0.0f, rot_eps = 0.0f;
+    float e_abs = 0.0f, e_sph = 0.0f, e_dir = 0.0f, rot_eps = 0.0f;
     // this lane's slab (lane mod K) of the pose's support-function transform
     const uint32_t my_k = lane % (uint32_t)K;
     const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
@@ -665,6 +708,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 }
                 rot_eps = __double2float_ru(dev) + 0x1p-22f;
             }
+            // rounding allowance of the directional gap below: the sphere
+            // bound's, grown with the matrix's largest stretch
+            e_dir = __builtin_fmaf(2.0f * rot_eps, e_sph, e_sph);
         }
 
         // ---- initial state ----
@@ -740,7 +786,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 // -------- transform A's records of the frame into B's frame --------
                 // lane = (record c, slab my_k), CPL records per pass, two passes
                 // at a time; each generator reads its slab's (lo, hi) pair at once
-                {
+                // (distance tests of AABB models read only the spheres below)
+                if constexpr (MODE != MODE_DIST || K != 3) {
                     const float4 x0 = xf[2 * my_k], x1 = xf[2 * my_k + 1];
                     const uint32_t up = __float_as_uint(x0.w);
                     const uint32_t a0 = (up & 0xFFu) >> 1, a1 = ((up >> 8) & 0xFFu) >> 1, a2 = ((up >> 16) & 0xFFu) >> 1;
@@ -804,12 +851,22 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         const float *tA = ta + 2 * K * ia;
                         const float *bB = rbnd + (size_t)recB * 2 * K;
                         if (MODE == MODE_DIST) {
-                            float g = 0.0f;
+                            // A lower bound on the distance of the two BVs (the largest of
+                            // the ones below); where the boxes overlap it is negative, and
+                            // then its value orders the traversal: the most deeply
+                            // overlapping pair goes first, which reaches close triangle
+                            // pairs (or an intersection, distance 0, which ends the pose)
+                            // sooner than taking overlapping pairs in lane order.
+                            // First: gaps of the 18-DOP slabs (AABB models skip them: beside
+                            // the directional gap below they pruned no more and cost time)
+                            float g = -INFINITY;
+                            if constexpr (K != 3) {
 #pragma unroll
-                            for (int k = 0; k < K; k++) {
-                                float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
-                                gk *= (k < 3 ? 1.0f : w_diag);
-                                g = fmaxf(g, gk);
+                                for (int k = 0; k < K; k++) {
+                                    float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
+                                    gk *= (k < 3 ? 1.0f : w_diag);
+                                    g = fmaxf(g, gk);
+                                }
                             }
                             // second lower bound: distance of the circumscribed spheres
                             float4 sa = tsph[2 * ia];
@@ -818,21 +875,10 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                             float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
                             float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
                             float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
-                            // third lower bound: separating-axis gaps along A's own
-                            // axes (the rotation's columns), with A's record as a box in
-                            // its frame and B's as an axis-aligned box; the allowances
-                            // cover non-unit, non-orthogonal columns and FP32 rounding
-                            const float4 ea = tsph[2 * ia + 1];
-                            float ga = -INFINITY;
-#pragma unroll
-                            for (int i = 0; i < 3; i++) {
-                                const float c0 = P.R[i], c1 = P.R[3 + i], c2 = P.R[6 + i];
-                                const float p = __builtin_fmaf(c0, dx, __builtin_fmaf(c1, dy, c2 * dz));
-                                const float rbi = __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
-                                ga = fmaxf(ga, fabsf(p) - (i == 0 ? ea.x : i == 1 ? ea.y : ea.z) - rbi);
-                            }
-                            ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
-                            lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), ga);
+                            // third lower bound: the gap along one well-chosen direction
+                            // (gaps along A's own axes, tried beside it, pruned no more)
+                            const float gd = dir_gap(P.R, sa, tsph[2 * ia + 1], bB, dx, dy, dz, hx, hy, hz, e_dir);
+                            lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), gd);  // g is -inf for AABB models
                             survive = lb <= tau;
                         } else {
                             bool sep = false;

@@ -189,6 +189,36 @@ def test_proximity_compressed_equals_uncompressed(proximity_results):
     _log(f"proximity stats compressed={out[True][2]} uncompressed={out[False][2]}")
 
 
+def test_proximity_dop18_distances_match_oracle_on_sample():
+    """The proximity meshes as 18-DOP models (BF 8, leaf 4; the slab gaps then
+    join the sphere and directional gaps in the distance bound): distances
+    within 1e-5 relative of the oracle on a sample of separated poses, zero on
+    colliding ones, and the 16-bit, binary16 and FP32 descriptors bit-identical."""
+    w = configs.WORKLOADS[2]
+    (va, ta), (vb, tb) = W.meshes(2)
+    A, B = W.oracle_meshes(2)
+    P = w.raw_poses()
+    idx = W.sample_indices(len(P), 96, seed=7)
+    cls = oracle.classify_batch(A, B, P[idx], w.margin(va, vb))
+    ref, _ = oracle.distance_batch(A, B, P[idx])
+    sep, col = cls == oracle.SEPARATED, cls == oracle.COLLIDING
+    assert sep.sum() > 60
+    got = {}
+    for bits in (16, cb.BITS_FP16, 0):
+        _log(f"proximity dop18 distance bits={bits}")
+        kw = dict(bv=cb.DOP18, branching=8, leaf_size=4, bits=bits)
+        ma, mb = cb.Model.build(va, ta, **kw).to(DEV), cb.Model.build(vb, tb, **kw).to(DEV)
+        d, st = cb.distance(ma, mb, torch.from_numpy(P[idx]).to(DEV))
+        assert (st.cpu().numpy() == 0).all()
+        got[bits] = d.cpu().numpy()
+        g = got[bits].astype(np.float64)
+        rel = np.abs(g[sep] - ref[sep]) / ref[sep]
+        assert rel.max() <= 1e-5, (bits, rel.max(), idx[sep][np.argmax(rel)])
+        assert (g[col] == 0).all()
+    assert np.array_equal(got[16].view(np.uint32), got[0].view(np.uint32))
+    assert np.array_equal(got[cb.BITS_FP16].view(np.uint32), got[0].view(np.uint32))
+
+
 # ---------------------------------------------------------------- edge cases and failure paths
 def test_empty_batch_is_a_noop():
     ma, mb = models(0)
