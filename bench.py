@@ -365,6 +365,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--large-obstacle-set", type=int, default=0, metavar="N",
                     help="also time the descriptor formats on N device copies of a 200k-triangle obstacle")
+    ap.add_argument("--proximity-only", action="store_true",
+                    help="time only the proximity distance workload (for kernel traces of the distance kernel)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -378,6 +380,12 @@ def main():
     from synth import configs
 
     dev = torch.device("cuda:0")
+    if args.proximity_only:
+        w2 = configs.WORKLOADS[2]
+        pr = run_distance(cb, w2, w2.bits, dev, args.steps, args.warmup)
+        print(json.dumps({"workload": w2.name, "steps": args.steps, "warmup": args.warmup,
+                          "proximity": summarize(pr, args.steps)}), flush=True)
+        return
     w = configs.WORKLOADS[1]
     main_r = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT)
     main_s = summarize(main_r, args.steps)
