@@ -9,7 +9,10 @@
   poses accepted by the pose-level margin; compressed == uncompressed on all;
 - proximity workload (50k icosphere vs 50k torus, AABB BF4 leaf 1, 8-bit and
   FP32): distances within 1e-5 relative of the oracle on a sample of
-  separated poses; compressed and uncompressed bit-identical on all;
+  separated poses; compressed and uncompressed bit-identical on all; the same
+  meshes as 18-DOP models (16-bit, binary16, FP32) against the oracle too;
+- near-touching poses offset along random directions (AABB and 18-DOP):
+  distances equal the oracle's, so no distance bound overshoots;
 - failure paths forced from the host (tiny stack, tiny pair buffer), empty
   and degenerate inputs, determinism.
 """
@@ -217,6 +220,46 @@ def test_proximity_dop18_distances_match_oracle_on_sample():
         assert (g[col] == 0).all()
     assert np.array_equal(got[16].view(np.uint32), got[0].view(np.uint32))
     assert np.array_equal(got[cb.BITS_FP16].view(np.uint32), got[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("bv", ["aabb", "dop18"])
+def test_near_touching_poses_in_every_direction_match_oracle(bv):
+    """Two 1,280-triangle icospheres placed almost touching, offset along
+    uniformly random directions (so the BV pairs near contact are offset
+    diagonally, where a distance bound along fixed axes is weakest and a
+    bound that overshoots the true distance would prune the closest pair):
+    distances within 1e-5 relative of the oracle, zero where they collide."""
+    _log(f"near-touching distances bv={bv}")
+    rng = np.random.default_rng(2012)
+    (va, ta), (vb, tb) = W.meshes(0)
+    A, B = W.oracle_meshes(0)
+    n = 256
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    R = poses.uniform_rotations(n, rng)
+    # at an offset of 2.4 the spheres (radii 0.9-1.1) are apart by d0; moving
+    # A closer by d0 - gap leaves them at least `gap` apart (the distance is
+    # 1-Lipschitz in the offset), near contact for convex-ish shapes; the
+    # last 32 poses go 0.02 past that and mostly collide
+    d0, _ = oracle.distance_batch(A, B, poses.compose(R, u * 2.4))
+    gap = np.exp(rng.uniform(np.log(1e-3), np.log(0.3), size=n))
+    gap[-32:] = -0.02
+    P = poses.compose(R, u * (2.4 - d0 + gap)[:, None])
+    if bv == "aabb":
+        kw = dict(bv=cb.AABB, branching=4, leaf_size=1, bits=8)
+    else:
+        kw = dict(bv=cb.DOP18, branching=8, leaf_size=4, bits=16)
+    ma, mb = cb.Model.build(va, ta, **kw).to(DEV), cb.Model.build(vb, tb, **kw).to(DEV)
+    d, st = cb.distance(ma, mb, torch.from_numpy(P).to(DEV))
+    cls = oracle.classify_batch(A, B, P, configs.WORKLOADS[0].margin(va, vb))
+    ref, _ = oracle.distance_batch(A, B, P)
+    sep, col = cls == oracle.SEPARATED, cls == oracle.COLLIDING
+    assert sep.sum() > 150 and col.sum() > 5 and np.median(ref[sep]) < 0.05
+    assert (st.cpu().numpy() == 0).all()
+    got = d.cpu().numpy().astype(np.float64)
+    rel = np.abs(got[sep] - ref[sep]) / ref[sep]
+    assert rel.max() <= 1e-5, (rel.max(), np.nonzero(sep)[0][np.argmax(rel)])
+    assert (got[col] == 0).all()
 
 
 # ---------------------------------------------------------------- edge cases and failure paths
