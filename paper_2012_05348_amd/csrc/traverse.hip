@@ -448,6 +448,12 @@ constexpr unsigned long long kWaitLimit = 1000000000ull;
 constexpr uint32_t kDonatePeriod = 8;
 // steps between refreshes of the shared per-pose answer (hit flag or best distance)
 constexpr uint32_t kSyncPeriod = 4;
+// distance queries between 18-DOP models with multi-triangle leaves: triangle
+// pairs screened per leaf step (by the distance of their boxes) before the
+// survivors get the full FP32 test, and how many times the usual number of
+// leaf pairs a leaf step waits for
+constexpr uint32_t kScreenMax = 256;
+constexpr uint32_t kScreenTrigMult = 4;
 // most items one balancing donation hands out
 constexpr uint32_t kMaxDonate = 32;
 // a unit hands work over only while it holds at least this many entries
@@ -985,7 +991,13 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             }
 
             // -------- leaf step --------
+            // distance queries whose leaves hold several triangles each screen
+            // the triangle pairs first (18-DOP models: the screening buffer
+            // shares LDS with the transformed records, which are dead here)
+            constexpr bool kScreens = MODE == MODE_DIST && K == 9;
+            const bool screen = kScreens && lq_trigger_full < (uint32_t)WAVE;
             uint32_t trig = lq_trigger_full < 1 ? 1 : lq_trigger_full;
+            if (screen) trig = min(trig * kScreenTrigMult, lim.leafq / 2u);
             if (MODE == MODE_DIST && best32 == INFINITY) trig = 1;
             if (lq_count > 0 && (lq_count >= trig || top == 0)) {
                 const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
@@ -999,115 +1011,167 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     if (MODE == MODE_DIST && lq_lb[slot] > tau) tasks = 0;
                 }
                 uint32_t incl = wave_incl_scan(tasks, lane);
-                uint64_t m_take = __ballot(lane < n_avail && incl <= (uint32_t)WAVE);
+                uint64_t m_take = __ballot(lane < n_avail && incl <= (screen ? kScreenMax : (uint32_t)WAVE));
                 uint32_t n_take = __popcll(m_take);
                 uint32_t total = n_take ? lane_of(incl, (int)n_take - 1) : 0u;
                 if (lane < n_take) scratch[lane] = incl;
                 wave_sync();
                 const uint32_t lq_old = lq_count;
                 lq_count -= n_take;
-                int res = 0;
-                float dres = INFINITY;
-                bool active = lane < total;
-                uint32_t triA = 0, triB = 0;
-                V3<float> a[3], b[3];
-                if (active) {
-                    // entry of this lane: first e with incl[e] > lane
+                // triangle pair number t of the taken leaf pairs
+                auto pair_of = [&](uint32_t t, uint32_t &tA, uint32_t &tB) {
+                    // its leaf pair: the first taken entry with incl > t
                     uint32_t lo = 0, hi = n_take - 1;
                     while (lo < hi) {
                         uint32_t mid = (lo + hi) >> 1;
-                        if (scratch[mid] > lane) hi = mid; else lo = mid + 1;
+                        if (scratch[mid] > t) hi = mid; else lo = mid + 1;
                     }
                     uint32_t excl = lo ? scratch[lo - 1] : 0u;
                     uint2 le = lq[lq_old - 1 - lo];
-                    uint32_t local = lane - excl, nb = topo_count(le.y);
+                    uint32_t local = t - excl, nb = topo_count(le.y);
                     uint32_t ia = (local * recip16(nb)) >> 16, ib = local - ia * nb;
-                    triA = topo_first(le.x) + ia;
-                    triB = topo_first(le.y) + ib;
-                    V3<float> a0[3];
-                    load_tri(MA.tris, triA, a0);
-                    load_tri(MB.tris, triB, b);
-#pragma unroll
-                    for (int v = 0; v < 3; v++) a[v] = xform_f32(P, a0[v]);
-                    // 0 disjoint, 1 intersecting, 2 undecided in FP32 (decided by the FP64 stage)
-                    res = tri_tri_f32(a, b);
-                    if (MODE == MODE_DIST) {
-                        // undecided pairs also get their FP32 feature distance:
-                        // it is accurate if they are disjoint and too large
-                        // (never too small) if they intersect, so the running
-                        // bound stays safe; the FP64 stage decides them
-                        float d32 = 0.0f;
-                        if (res != 1) {
-                            V3<float> ar[3], br[3];
-#pragma unroll
-                            for (int v = 0; v < 3; v++) {
-                                ar[v] = vsub(a[v], a[0]);
-                                br[v] = vsub(b[v], a[0]);
+                    tA = topo_first(le.x) + ia;
+                    tB = topo_first(le.y) + ib;
+                };
+                uint32_t n_full = total;
+                uint2 *tq = (uint2 *)ta;
+                static_assert(8 * 9 * TA_MAX >= 8 * (int)kScreenMax, "the screening buffer fits the transformed records");
+                if (screen) {
+                    // screening: a pair whose boxes (A's triangle placed by the
+                    // pose, in FP32) are farther apart than the bound cannot be
+                    // the closest one; e_abs covers the FP32 placement
+                    n_full = 0;
+                    for (uint32_t c0 = 0; c0 < total; c0 += WAVE) {
+                        const uint32_t t = c0 + lane;
+                        bool keep = false;
+                        uint32_t tA = 0, tB = 0;
+                        if (t < total) {
+                            pair_of(t, tA, tB);
+                            V3<float> a0[3], bb[3];
+                            load_tri(MA.tris, tA, a0);
+                            load_tri(MB.tris, tB, bb);
+                            float g2 = 0.0f;
+                            {
+                                const V3<float> p0 = xform_f32(P, a0[0]), p1 = xform_f32(P, a0[1]), p2 = xform_f32(P, a0[2]);
+                                const float ga = fmaxf(fminf(fminf(p0.x, p1.x), p2.x) - fmaxf(fmaxf(bb[0].x, bb[1].x), bb[2].x),
+                                                       fminf(fminf(bb[0].x, bb[1].x), bb[2].x) - fmaxf(fmaxf(p0.x, p1.x), p2.x));
+                                const float gb = fmaxf(fminf(fminf(p0.y, p1.y), p2.y) - fmaxf(fmaxf(bb[0].y, bb[1].y), bb[2].y),
+                                                       fminf(fminf(bb[0].y, bb[1].y), bb[2].y) - fmaxf(fmaxf(p0.y, p1.y), p2.y));
+                                const float gc = fmaxf(fminf(fminf(p0.z, p1.z), p2.z) - fmaxf(fmaxf(bb[0].z, bb[1].z), bb[2].z),
+                                                       fminf(fminf(bb[0].z, bb[1].z), bb[2].z) - fmaxf(fmaxf(p0.z, p1.z), p2.z));
+                                const float x = fmaxf(ga, 0.0f), y = fmaxf(gb, 0.0f), z = fmaxf(gc, 0.0f);
+                                g2 = __builtin_fmaf(x, x, __builtin_fmaf(y, y, z * z));
                             }
-                            d32 = sqrtf(tri_tri_dist2(ar, br));
+                            keep = sqrtf(g2) * (1.0f - 0x1p-20f) - e_abs <= tau;
                         }
-                        dres = d32;
+                        const uint64_t mk = __ballot(keep);
+                        if (keep) tq[n_full + mbcnt(mk)] = make_uint2(tA, tB);
+                        n_full += __popcll(mk);
                     }
+                    cnt.tri_bytes += 72ull * total;
+                    wave_sync();
                 }
-                cnt.tri_tests += total;
-                cnt.leaf_steps++;
-                cnt.tri_bytes += 72ull * total;
-                // leaf pairs for the FP64 stage: undecided intersections, and
-                // distances that could be the minimum
-                bool defer;
-                if (MODE == MODE_BOOL || MODE == MODE_PAIRS) {
-                    bool h = active && res == 1;
-                    defer = active && res == 2;
-                    uint64_t mh = __ballot(h);
-                    if (mh) {
-                        hit = true;
-                        if (lane == 0) {
-                            q.hit[pose] = 1;
-                            if (MODE == MODE_BOOL && shared) rmw_xchg(&q.ws.hitw[pose], 1u);
+                for (uint32_t p0 = 0; p0 < n_full; p0 += WAVE) {
+                    int res = 0;
+                    float dres = INFINITY;
+                    const uint32_t n_pass = min(n_full - p0, (uint32_t)WAVE);
+                    bool active = lane < n_pass;
+                    uint32_t triA = 0, triB = 0;
+                    V3<float> a[3], b[3];
+                    if (active) {
+                        if (screen) {
+                            const uint2 pr = tq[p0 + lane];
+                            triA = pr.x;
+                            triB = pr.y;
+                        } else {
+                            pair_of(lane, triA, triB);
+                        }
+                        V3<float> a0[3];
+                        load_tri(MA.tris, triA, a0);
+                        load_tri(MB.tris, triB, b);
+#pragma unroll
+                        for (int v = 0; v < 3; v++) a[v] = xform_f32(P, a0[v]);
+                        // 0 disjoint, 1 intersecting, 2 undecided in FP32 (decided by the FP64 stage)
+                        res = tri_tri_f32(a, b);
+                        if (MODE == MODE_DIST) {
+                            // undecided pairs also get their FP32 feature distance:
+                            // it is accurate if they are disjoint and too large
+                            // (never too small) if they intersect, so the running
+                            // bound stays safe; the FP64 stage decides them
+                            float d32 = 0.0f;
+                            if (res != 1) {
+                                V3<float> ar[3], br[3];
+#pragma unroll
+                                for (int v = 0; v < 3; v++) {
+                                    ar[v] = vsub(a[v], a[0]);
+                                    br[v] = vsub(b[v], a[0]);
+                                }
+                                d32 = sqrtf(tri_tri_dist2(ar, br));
+                            }
+                            dres = d32;
                         }
                     }
-                    if (MODE == MODE_PAIRS && mh) {
-                        uint32_t nh = __popcll(mh);
-                        uint32_t b0 = 0;
-                        if (lane == 0) b0 = atomicAdd(&hdr->pair_count, nh);
-                        b0 = uni(b0);
-                        if (h) {
-                            uint32_t idx = b0 + mbcnt(mh);
-                            if (idx < q.pair_cap)
-                                q.ws.pair_raw[idx] = make_uint4(pose, MA.perm[triA], MB.perm[triB], 0u);
+                    cnt.tri_tests += n_pass;
+                    cnt.leaf_steps++;
+                    if (!screen) cnt.tri_bytes += 72ull * n_pass;
+                    // leaf pairs for the FP64 stage: undecided intersections, and
+                    // distances that could be the minimum
+                    bool defer;
+                    if (MODE == MODE_BOOL || MODE == MODE_PAIRS) {
+                        bool h = active && res == 1;
+                        defer = active && res == 2;
+                        uint64_t mh = __ballot(h);
+                        if (mh) {
+                            hit = true;
+                            if (lane == 0) {
+                                q.hit[pose] = 1;
+                                if (MODE == MODE_BOOL && shared) rmw_xchg(&q.ws.hitw[pose], 1u);
+                            }
                         }
-                        if (b0 + nh > q.pair_cap) pair_overflow = true;
+                        if (MODE == MODE_PAIRS && mh) {
+                            uint32_t nh = __popcll(mh);
+                            uint32_t b0 = 0;
+                            if (lane == 0) b0 = atomicAdd(&hdr->pair_count, nh);
+                            b0 = uni(b0);
+                            if (h) {
+                                uint32_t idx = b0 + mbcnt(mh);
+                                if (idx < q.pair_cap)
+                                    q.ws.pair_raw[idx] = make_uint4(pose, MA.perm[triA], MB.perm[triB], 0u);
+                            }
+                            if (b0 + nh > q.pair_cap) pair_overflow = true;
+                        }
+                    } else {
+                        // a certified intersection is distance 0: the pose is done
+                        if (__ballot(active && res == 1)) {
+                            best64 = 0.0;
+                            dres = 0.0f;
+                        }
+                        float wmin = wave_min(dres);
+                        if (wmin < best32) {
+                            best32 = wmin;
+                            if (shared && lane == 0)
+                                __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best32), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        defer = active && (res == 2 || (res == 0 && dres <= add_up(best32, 2.0f * e_abs)));
                     }
-                } else {
-                    // a certified intersection is distance 0: the pose is done
-                    if (__ballot(active && res == 1)) {
-                        best64 = 0.0;
-                        dres = 0.0f;
+                    const uint64_t md = __ballot(defer);
+                    if (md) {
+                        const uint32_t nd = __popcll(md);
+                        uint32_t f0 = 0;
+                        if (lane == 0) f0 = atomicAdd(&hdr->fix_count, nd);
+                        f0 = uni(f0);
+                        if (defer) {
+                            const uint32_t idx = f0 + mbcnt(md);
+                            // an undecided pair is stored with distance 0, which the
+                            // FP64 stage's final-bound filter always keeps
+                            const uint32_t dw = res == 2 ? 0u : __float_as_uint(dres);
+                            if (idx < q.ws.fix_cap) q.ws.fix[idx] = make_uint4(pose, triA, triB, dw);
+                        }
+                        if (f0 + nd > q.ws.fix_cap) fix_overflow = true;
+                        cnt.tri_fp64 += nd;
                     }
-                    float wmin = wave_min(dres);
-                    if (wmin < best32) {
-                        best32 = wmin;
-                        if (shared && lane == 0)
-                            __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best32), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    defer = active && (res == 2 || (res == 0 && dres <= add_up(best32, 2.0f * e_abs)));
-                }
-                const uint64_t md = __ballot(defer);
-                if (md) {
-                    const uint32_t nd = __popcll(md);
-                    uint32_t f0 = 0;
-                    if (lane == 0) f0 = atomicAdd(&hdr->fix_count, nd);
-                    f0 = uni(f0);
-                    if (defer) {
-                        const uint32_t idx = f0 + mbcnt(md);
-                        // an undecided pair is stored with distance 0, which the
-                        // FP64 stage's final-bound filter always keeps
-                        const uint32_t dw = res == 2 ? 0u : __float_as_uint(dres);
-                        if (idx < q.ws.fix_cap) q.ws.fix[idx] = make_uint4(pose, triA, triB, dw);
-                    }
-                    if (f0 + nd > q.ws.fix_cap) fix_overflow = true;
-                    cnt.tri_fp64 += nd;
+                    if constexpr (!kScreens) break;  // one pass: at most 64 pairs were taken
                 }
                 wave_sync();
                 continue;
