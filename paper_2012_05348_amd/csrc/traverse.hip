@@ -125,7 +125,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.frame_end = take(4 * MAX_FRAMES);
     L.rtopo = take(4 * lim.records);
     L.rbnd = take(8 * K * lim.records);
-    L.ta = take(8 * K * TA_MAX);
+    L.ta = (mode == MODE_DIST && K == 3) ? o : take(8 * K * TA_MAX);  // AABB distance tests read no transform
     L.tsph = take(32 * TA_MAX);
     L.ent = take(4 * lim.entries);
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
@@ -476,9 +476,10 @@ constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 // is when waiting waves exit.  Per-pose answers (hit flag, best distances)
 // are merged in device memory, so results do not depend on the split.
 // ---------------------------------------------------------------------------
-// Collision modes fit 3 waves per SIMD (168 VGPRs); distance mode needs more.
+// Collision modes and distance queries of AABB models fit 3 waves per SIMD
+// (168 VGPRs); distance queries of 18-DOP models need more.
 template <int K, int BITS, int MODE>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(MODE == MODE_DIST ? 2 : 3)))
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu((MODE == MODE_DIST && K == 9) ? 2 : 3)))
 void traverse_kernel(QueryArgs q, StackLimits lim)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1755,7 +1756,9 @@ size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return m
 StackLimits default_limits(uint32_t K, int mode)
 {
     // branch-and-bound keeps many more pairs pending than collision queries
-    if (mode == MODE_DIST) return K == 9 ? StackLimits{160, 512, 128} : StackLimits{256, 768, 128};
+    // (AABB models: 512 entries, so that 10 waves fit a CU; with 768 and 8
+    // waves the proximity workload was 5 % slower)
+    if (mode == MODE_DIST) return K == 9 ? StackLimits{160, 512, 128} : StackLimits{256, 512, 128};
     return K == 9 ? StackLimits{80, 192, 128} : StackLimits{160, 384, 128};
 }
 
