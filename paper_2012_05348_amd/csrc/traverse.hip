@@ -1755,10 +1755,11 @@ size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return m
 
 StackLimits default_limits(uint32_t K, int mode)
 {
-    // branch-and-bound keeps many more pairs pending than collision queries
-    // (AABB models: 512 entries, so that 10 waves fit a CU; with 768 and 8
-    // waves the proximity workload was 5 % slower)
-    if (mode == MODE_DIST) return K == 9 ? StackLimits{160, 512, 128} : StackLimits{256, 512, 128};
+    // branch-and-bound keeps many more pairs pending than collision queries;
+    // the sizes let 10 waves (AABB) or 8 waves (18-DOP, the most its
+    // registers allow) fit a CU, about 5 % faster than 8 and 7 waves with
+    // the larger stacks used before (768 and 512 entries)
+    if (mode == MODE_DIST) return K == 9 ? StackLimits{144, 448, 128} : StackLimits{256, 512, 128};
     return K == 9 ? StackLimits{80, 192, 128} : StackLimits{160, 384, 128};
 }
 
