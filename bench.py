@@ -113,6 +113,7 @@ def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0):
     kern_ms = traversal_kernel_ms(cb, step, ws.buf, min(steps, 10))
     info = ma.info()
     return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=status_ok, hits=int(hit.sum().item()),
+                hit=hit.cpu().numpy(),
                 info=info, descriptor_bytes=info["descriptor_bytes"] + mb.info()["descriptor_bytes"], kern_ms=kern_ms)
 
 
@@ -263,6 +264,22 @@ def run_serving(cb, dev, n_requests=1500):
     rate = sat["requests_per_sec"]
     out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests,
            "saturation": {k: sat[k] for k in ("poses_per_sec", "requests_per_sec", "launches", "p50_ms", "p99_ms")}}
+    out["saturation"]["status_ok"] = bool((sat["status"] == 0).all())
+    # each served request against its plain query run alone (the judge of the batched path)
+    progress("serving: every request of the saturation run against its plain query")
+    import torch
+    equal = True
+    for r in range(len(sat_req)):
+        sl = slice(sat_req.first[r], sat_req.first[r] + sat_req.count[r])
+        Pr = torch.from_numpy(sat_req.poses[sl]).to(dev)
+        m = oset.models[int(sat_req.obstacle[r])]
+        if sat_req.kind[r] == serve.COLLIDE:
+            h, _ = cb.collide(link, m, Pr)
+            equal &= bool(np.array_equal(h.cpu().numpy(), sat["hit"][sl]))
+        else:
+            d, _ = cb.distance(link, m, Pr)
+            equal &= bool(np.array_equal(d.cpu().numpy().view(np.uint32), sat["dist"][sl].view(np.uint32)))
+    out["saturation"]["answers_equal_plain_queries"] = equal
     progress(f"serving: saturation {sat['poses_per_sec']:.3g} poses/s, {rate:.0f} requests/s")
     for frac in (0.5, 0.8, 0.95):
         req = serve.make_requests(n_requests, frac * rate, w.n_obstacles, rng)
@@ -316,44 +333,107 @@ def run_large_obstacle_set(cb, dev, n_obstacles=192, n_poses=32768, calls=9):
     return out
 
 
-def cpu_baseline(w, threads, budget_s=10.0):
-    """The FP64 oracle (Algorithm 1 over its own binary AABB tree) timed on the
-    host: repeated passes over the workload's poses until at least budget_s
-    seconds of work have run (at most 512 passes; for a slow workload one pass
-    over a prefix sized to the budget)."""
-    import oracle
-    progress("cpu baseline (oracle)")
-    (va, ta), (vb, tb) = w.meshes()
-    A, B = oracle.Mesh(va, ta), oracle.Mesh(vb, tb)
-    P = w.raw_poses()
-    n = len(P)
-    # size the sample from a short probe so slow workloads stay bounded
-    probe = P[: min(n, 256)]
+def host_cpus():
+    """The host CPU as this process sees it: model, nproc, the CPUs it may run
+    on, the cgroup's CPU quota, and the thread count the oracle uses (the
+    smallest of those and OMP_NUM_THREADS, the per-GPU CPU share where set)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()
+            if q != "max":
+                quota = max(1, int(int(q) / int(per)))
+    except (OSError, ValueError):
+        pass
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or None
+    threads = min(x for x in (os.cpu_count() or 1, aff, quota, omp) if x)
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff, "cgroup_cpus": quota,
+            "omp_num_threads": omp, "threads_used": threads}
+
+
+def time_oracle(run, n, threads, budget_s):
+    """Oracle poses/s over a bounded sample: run(k, threads) runs the first k
+    poses.  A short probe sizes the sample to about budget_s seconds; fast
+    workloads repeat passes over all n poses until budget_s has elapsed (at
+    most 512); one thread runs a prefix of about budget_s / 4 seconds."""
+    k0 = min(n, 64)
     t0 = time.perf_counter()
-    run = oracle.distance_batch if w.query == "distance" else oracle.collide_batch
-    run(A, B, probe, threads=threads)
-    per_pose = (time.perf_counter() - t0) / len(probe)
-    n_sample = int(min(n, max(256, budget_s / max(per_pose, 1e-9))))
-    sample = P[:n_sample]
+    run(k0, threads)
+    per_pose = (time.perf_counter() - t0) / k0
+    k = int(min(n, max(k0, budget_s / max(per_pose, 1e-9))))
     passes = 0
     t0 = time.perf_counter()
     while True:
-        run(A, B, sample, threads=threads)
+        run(k, threads)
         passes += 1
         dt = time.perf_counter() - t0
-        if n_sample < n or dt >= budget_s or passes >= 512:
+        if k < n or dt >= budget_s or passes >= 512:
             break
-    progress(f"  oracle: {passes} pass(es) over {n_sample} poses in {dt:.2f} s")
-    # the same oracle on one thread, over a shorter sample (about budget_s / 4)
-    n1 = int(min(n, max(64, budget_s / 4 / max(per_pose * threads, 1e-9))))
-    t0 = time.perf_counter()
-    run(A, B, P[:n1], threads=1)
-    dt1 = time.perf_counter() - t0
-    progress(f"  oracle, one thread: {n1} poses in {dt1:.2f} s")
-    return {"value": passes * n_sample / dt, "unit": "poses/s", "cores": threads, "kind": "oracle",
-            "sample": f"{passes} pass(es) over the first {n_sample} of the {n} poses ({dt:.1f} s); "
-                      "FP64 Algorithm 1 on the oracle's own binary AABB tree, early exit per pose",
-            "single_thread": {"value": n1 / dt1, "unit": "poses/s", "sample": f"the first {n1} poses ({dt1:.1f} s)"}}
+    k1 = int(min(n, max(16, budget_s / 4 / max(per_pose * threads, 1e-9))))
+    t1 = time.perf_counter()
+    run(k1, 1)
+    dt1 = time.perf_counter() - t1
+    return {"value": passes * k / dt, "unit": "poses/s", "cores": threads, "kind": "oracle",
+            "sample": f"{passes} pass(es) over the first {k} of the {n} poses ({dt:.1f} s)",
+            "single_thread": {"value": k1 / dt1, "unit": "poses/s", "sample": f"the first {k1} poses ({dt1:.1f} s)"}}
+
+
+def cpu_baseline(w, threads, budget_s=10.0):
+    """The FP64 oracle (Algorithm 1 over its own binary AABB tree, early exit
+    per pose) on the scaled workload's poses, timed on the host."""
+    import oracle
+    progress("cpu baseline (oracle): scaled")
+    (va, ta), (vb, tb) = w.meshes()
+    A, B = oracle.Mesh(va, ta), oracle.Mesh(vb, tb)
+    P = w.raw_poses()
+    r = time_oracle(lambda k, t: oracle.collide_batch(A, B, P[:k], threads=t), len(P), threads, budget_s)
+    r["sample"] += "; FP64 Algorithm 1 on the oracle's own binary AABB tree, early exit per pose"
+    progress(f"  oracle: {r['value']:.4g} poses/s on {threads} threads, {r['single_thread']['value']:.4g} on one")
+    return r
+
+
+def cpu_baselines_other(threads, budget_s=6.0):
+    """The oracle on the tiny (pair lists: full enumeration per pose),
+    proximity (branch-and-bound distance) and batched (per-obstacle early-exit
+    booleans) workloads, each on the same raw poses as the GPU run."""
+    import oracle
+    from synth import configs
+    out = {}
+    w0, w2 = configs.WORKLOADS[0], configs.WORKLOADS[2]
+    for key, w, fn in (("tiny_pairs", w0, oracle.pair_count_batch), ("proximity", w2, oracle.distance_batch)):
+        progress(f"cpu baseline (oracle): {key}")
+        (va, ta), (vb, tb) = w.meshes()
+        A, B = oracle.Mesh(va, ta), oracle.Mesh(vb, tb)
+        P = w.raw_poses()
+        out[key] = time_oracle(lambda k, t: fn(A, B, P[:k], threads=t), len(P), threads, budget_s)
+    progress("cpu baseline (oracle): batched")
+    wb = configs.BATCHED
+    P, obj = wb.raw_poses()
+    link = oracle.Mesh(*wb.link_mesh())
+    obs = {}
+
+    def run_batched(k, t):
+        for o in np.unique(obj[:k]):
+            if o not in obs:
+                obs[o] = oracle.Mesh(*wb.obstacle_mesh(int(o)))
+            idx = np.nonzero(obj[:k] == o)[0]
+            oracle.collide_batch(link, obs[o], P[idx], threads=t)
+
+    # oracle trees of the obstacles are built outside the timed passes
+    for o in np.unique(obj):
+        obs[o] = oracle.Mesh(*wb.obstacle_mesh(int(o)))
+    out["batched"] = time_oracle(run_batched, len(P), threads, budget_s)
+    return out
 
 
 def main():
@@ -441,7 +521,7 @@ def main():
     if not args.no_extra:
         unc = run_collide(cb, w, 0, dev, args.steps, args.warmup, cb.EARLY_EXIT)
         out["uncompressed"] = summarize(unc, args.steps)
-        out["uncompressed"]["hits_equal"] = unc["hits"] == main_r["hits"]
+        out["uncompressed"]["hits_equal"] = bool(np.array_equal(unc["hit"], main_r["hit"]))
         out["compression"] = {
             "descriptor_bytes_compressed": main_s["descriptor_bytes"],
             "descriptor_bytes_fp32": out["uncompressed"]["descriptor_bytes"],
@@ -452,7 +532,7 @@ def main():
         # the paper's half-precision descriptors (section III.A), a third point
         f16 = run_collide(cb, w, cb.BITS_FP16, dev, args.steps, args.warmup, cb.EARLY_EXIT)
         out["fp16"] = summarize(f16, args.steps)
-        out["fp16"]["hits_equal"] = f16["hits"] == main_r["hits"]
+        out["fp16"]["hits_equal"] = bool(np.array_equal(f16["hit"], main_r["hit"]))
         out["compression"]["descriptor_bytes_fp16"] = out["fp16"]["descriptor_bytes"]
         out["compression"]["bv_test_inflation_fp16"] = (out["fp16"]["bv_tests_per_call"] /
                                                         max(1, out["uncompressed"]["bv_tests_per_call"]))
@@ -467,7 +547,18 @@ def main():
     if args.large_obstacle_set:
         out["large_obstacle_set"] = run_large_obstacle_set(cb, dev, args.large_obstacle_set)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, threads=min(16, os.cpu_count() or 1))
+        host = host_cpus()
+        out["cpu_baseline"] = cpu_baseline(w, threads=host["threads_used"])
+        out["cpu_baseline"]["host"] = host
+        out["cpu_baseline"]["gpu_over_oracle"] = out["value"] / out["cpu_baseline"]["value"]
+        if not args.no_extra:
+            other = cpu_baselines_other(host["threads_used"])
+            gpu = {"tiny_pairs": out["tiny_pairs"]["poses_per_sec"], "proximity": out["proximity"]["poses_per_sec"],
+                   "batched": out["batched"]["poses_per_sec"]}
+            for k, r in other.items():
+                r["gpu_poses_per_sec"] = gpu[k]
+                r["gpu_over_oracle"] = gpu[k] / r["value"]
+            out["cpu_baseline"]["other_workloads"] = other
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib << 20
         src = torch.empty(n, dtype=torch.uint8, device=dev)

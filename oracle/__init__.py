@@ -47,6 +47,7 @@ def lib():
             "orc_classify": (i32, [P, P, P, d, i32]),
             "orc_collide_batch": (None, [P, P, P, u64, i32, P, P]),
             "orc_distance_batch": (None, [P, P, P, u64, i32, P, P]),
+            "orc_pair_count_batch": (None, [P, P, P, u64, i32, P, P]),
             "orc_classify_batch": (None, [P, P, P, u64, d, i32, i32, P]),
             "orc_blob_info": (i32, [P, sz, P]),
             "orc_blob_decode": (i32, [P, sz, P, P, sz]),
@@ -199,6 +200,16 @@ def distance_batch(A: Mesh, B: Mesh, poses, threads=None):
     out = np.zeros(len(P), dtype=np.float64)
     cnt = np.zeros(2, dtype=np.uint64)
     lib().orc_distance_batch(A.handle, B.handle, _p(P), len(P), int(threads or os.cpu_count() or 1), _p(out), _p(cnt))
+    return out, cnt
+
+
+def pair_count_batch(A: Mesh, B: Mesh, poses, threads=None):
+    """Number of intersecting triangle pairs per pose (full enumeration, no early exit)."""
+    P = _poses(poses)
+    out = np.zeros(len(P), dtype=np.uint64)
+    cnt = np.zeros(2, dtype=np.uint64)
+    lib().orc_pair_count_batch(A.handle, B.handle, _p(P), len(P), int(threads or os.cpu_count() or 1), _p(out),
+                               _p(cnt))
     return out, cnt
 
 

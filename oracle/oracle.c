@@ -267,7 +267,8 @@ EXPORT int orc_tt_interval(const double *a9, const double *b9)
 /* triangle-triangle distance                                          */
 /* ------------------------------------------------------------------ */
 /* closest point of triangle t to p: classify p against the Voronoi regions
- * of the vertices, edges and face (barycentric region tests) */
+ * of the vertices, edges and face (barycentric region tests); the textbook
+ * method of Ericson, Real-Time Collision Detection (2005), section 5.1.5 */
 static void closest_pt_tri(const double *p, const v3 *t, double *out)
 {
     v3 ab, ac, ap, bp, cp;
@@ -314,7 +315,7 @@ EXPORT double orc_pt_tri_dist(const double *p, const double *t9)
 /* squared distance between segments p1q1 and p2q2 (minimise the convex
  * quadratic |P(s) - Q(t)|^2 over [0,1]^2: interior stationary point when the
  * segments are not parallel, then clamp and re-solve for the other
- * parameter) */
+ * parameter; Ericson, Real-Time Collision Detection, section 5.1.9) */
 static double seg_seg_dist2(const double *p1, const double *q1, const double *p2, const double *q2)
 {
     v3 d1, d2, r;
@@ -775,12 +776,12 @@ EXPORT int orc_classify(const void *A, const void *B, const float *pose, double 
 /* batches over poses on a pthread pool                                 */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int kind; /* 0 collide (bool, early exit), 1 distance, 2 classify */
+    int kind; /* 0 collide (bool, early exit), 1 distance, 2 classify, 3 count colliding pairs */
     const void *A, *B;
     const float *poses;
     uint64_t n;
     double m; int pair_level;
-    uint8_t *u8_out; double *f64_out;
+    uint8_t *u8_out; double *f64_out; uint64_t *u64_out;
     uint64_t next;
     pthread_mutex_t mu;
     uint64_t counters[2];
@@ -798,7 +799,8 @@ static void *batch_worker(void *arg)
         const float *p = b->poses + 12 * i;
         if (b->kind == 0) b->u8_out[i] = (uint8_t)orc_collide(b->A, b->B, p, 1, NULL, 0, NULL, cnt);
         else if (b->kind == 1) b->f64_out[i] = orc_distance(b->A, b->B, p, cnt);
-        else b->u8_out[i] = (uint8_t)orc_classify(b->A, b->B, p, b->m, b->pair_level);
+        else if (b->kind == 2) b->u8_out[i] = (uint8_t)orc_classify(b->A, b->B, p, b->m, b->pair_level);
+        else orc_collide(b->A, b->B, p, 0, NULL, 0, &b->u64_out[i], cnt);
     }
     pthread_mutex_lock(&b->mu);
     b->counters[0] += cnt[0]; b->counters[1] += cnt[1];
@@ -834,6 +836,17 @@ EXPORT void orc_distance_batch(const void *A, const void *B, const float *poses,
     batch_t b;
     memset(&b, 0, sizeof b);
     b.kind = 1; b.A = A; b.B = B; b.poses = poses; b.n = n; b.f64_out = dist;
+    run_batch(&b, nthreads, counters);
+}
+
+/* number of intersecting triangle pairs per pose (the full enumeration of
+ * Algorithm 1 without early exit, as for pair lists) */
+EXPORT void orc_pair_count_batch(const void *A, const void *B, const float *poses, uint64_t n, int nthreads,
+                                 uint64_t *count, uint64_t *counters)
+{
+    batch_t b;
+    memset(&b, 0, sizeof b);
+    b.kind = 3; b.A = A; b.B = B; b.poses = poses; b.n = n; b.u64_out = count;
     run_batch(&b, nthreads, counters);
 }
 

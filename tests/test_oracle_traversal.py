@@ -157,7 +157,9 @@ def test_batches_match_single_calls():
     hits, _ = oracle.collide_batch(A, B, P, threads=4)
     dists, _ = oracle.distance_batch(A, B, P, threads=4)
     cls = oracle.classify_batch(A, B, P, 1e-3, threads=4)
+    counts, _ = oracle.pair_count_batch(A, B, P, threads=4)
     for i, p in enumerate(P):
+        assert counts[i] == len(oracle.brute_pairs(A, B, p))
         assert hits[i] == oracle.collide(A, B, p)[0]
         assert dists[i] == oracle.distance(A, B, p)[0]
         assert cls[i] == oracle.classify(A, B, p, 1e-3)
