@@ -128,6 +128,9 @@ cbvh_status cbvh_upload(const cbvh_model *m, void *dev, size_t capacity, void *s
 #define CBVH_POSE_PAIR_OVERFLOW 2u  /* pair buffer full; this pose's pair list is incomplete */
 #define CBVH_POSE_FP64_OVERFLOW 3u  /* workspace buffer of leaf pairs for FP64 re-evaluation full; results invalid */
 #define CBVH_POSE_BAD_OBSTACLE 4u   /* batched queries: the pose's obstacle index is out of range; results invalid */
+#define CBVH_POSE_INCOMPLETE 5u     /* a wavefront gave up waiting for handed-over work (the wait limit), so work
+                                       of this query may have been lost; set on every pose that has no other
+                                       failure; results invalid (the query's wait_timeouts counter is 1) */
 
 /* Workspace bytes (device, caller-owned, 256-byte aligned) for a query on
  * models a and b with n poses. */
@@ -239,7 +242,8 @@ typedef struct {
     uint64_t t_drain;        /* ... when a wave first found the pose queue empty */
     uint64_t t_end;          /* ... when the last wave exited */
     uint64_t max_pose_steps; /* most traversal steps (node + leaf) one work unit needed */
-    uint64_t wait_timeouts;  /* 1 if a wavefront gave up waiting for work (never expected; results invalid) */
+    uint64_t wait_timeouts;  /* 1 if a wavefront gave up waiting for work (never expected; every pose is then
+                                CBVH_POSE_INCOMPLETE unless flagged otherwise) */
     uint64_t node_steps;     /* node steps: one frame of children decoded and tested (up to 64 records) */
     uint64_t leaf_steps;     /* leaf steps: up to 64 triangle pairs tested */
 } cbvh_stats_t;
@@ -251,6 +255,15 @@ cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats
  * 0 restores the defaults.  Lets tests force the donation path from the
  * host.  Affects subsequent queries of this process. */
 cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records);
+
+/* How long a wavefront waiting for handed-over work waits before it gives
+ * up, in ticks of the 100 MHz device clock (0 restores the default, 10 s;
+ * at most 1000 s).  A query in which any wavefront gave up flags its poses
+ * CBVH_POSE_INCOMPLETE; every kernel still exits.  Waiting normally ends
+ * within microseconds; the limit guards against a stalled device, and a
+ * tiny value lets tests force the incomplete path from the host.  Affects
+ * subsequent queries of this process. */
+cbvh_status cbvh_set_wait_limit(uint64_t ticks);
 
 /* Thread-local message describing the last failure (never NULL). */
 const char *cbvh_last_error(void);

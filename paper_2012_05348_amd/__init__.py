@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libcbvh.so")
 AABB, DOP18 = 0, 1
 BITS_FP16 = 0x8010  # half-precision absolute descriptors (CBVH_BITS_FP16)
 EARLY_EXIT, PAIRS, NO_SPLIT = 0x1, 0x2, 0x4
-POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW, POSE_BAD_OBSTACLE = 0, 1, 2, 3, 4
+POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW, POSE_BAD_OBSTACLE, POSE_INCOMPLETE = range(6)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_CAPACITY", 5: "E_UNSUPPORTED", 6: "E_FORMAT"}
 
 
@@ -85,6 +85,7 @@ def lib():
             "cbvh_decode_all": (st, [P, P, P, P]),
             "cbvh_stats": (st, [P, sz, C.POINTER(Stats), P]),
             "cbvh_set_stack_limits": (st, [u32, u32]),
+            "cbvh_set_wait_limit": (st, [C.c_uint64]),
             "cbvh_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -224,6 +225,10 @@ def cbvh_stats(workspace, stream=None) -> dict:
 
 def cbvh_set_stack_limits(entries=0, records=0):
     _check(lib().cbvh_set_stack_limits(entries, records))
+
+
+def cbvh_set_wait_limit(ticks=0):
+    _check(lib().cbvh_set_wait_limit(ticks))
 
 
 def cbvh_last_error() -> str:

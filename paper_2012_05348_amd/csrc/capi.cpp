@@ -39,6 +39,10 @@ cbvh_status fail_hip(hipError_t e, const char *what)
 }
 
 std::atomic<uint32_t> g_limit_entries{0}, g_limit_records{0};
+// how long a waiting wave waits for a work item before it gives up and the
+// query's poses are flagged incomplete: 10 s of the 100 MHz device clock
+constexpr uint64_t kDefaultWaitTicks = 1000000000ull;
+std::atomic<uint64_t> g_wait_ticks{kDefaultWaitTicks};
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
@@ -82,7 +86,7 @@ struct WsPlan {
     uint32_t item_cap, item_words, fix_cap;
 };
 
-WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
+WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap, uint64_t item_cap_max = 1ull << 24)
 {
     WsPlan p;
     uint64_t o = 0;
@@ -95,7 +99,7 @@ WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap)
     // donated work items (slots are not reused within a query): four per
     // pose plus slack; a donation that finds the queue full is not made
     uint64_t cap = 4ull * n + 262144ull;
-    if (cap > (1ull << 24)) cap = 1ull << 24;
+    if (cap > item_cap_max) cap = item_cap_max;
     p.item_cap = (uint32_t)cap;
     bool dist = mode == cbvh::MODE_DIST, pairs = mode == cbvh::MODE_PAIRS;
     p.hdr = take(sizeof(cbvh::WsHeader));
@@ -134,7 +138,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
                       const float *poses, uint32_t n, int mode, uint32_t flags, uint8_t *hit, float *dist,
                       uint32_t *pairs, uint32_t pair_cap, uint32_t *pair_offsets, uint8_t *status, void *ws,
                       size_t ws_bytes, void *stream, const cbvh_obstacles *obs = nullptr,
-                      const uint32_t *pose_obj = nullptr)
+                      const uint32_t *pose_obj = nullptr, uint64_t item_cap_max = 1ull << 24)
 {
     cbvh_status st;
     if (obs) {
@@ -160,7 +164,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     if (n > (1u << 30)) return fail(CBVH_E_INVALID, "too many poses");
     if (!ws) return fail(CBVH_E_INVALID, "workspace is NULL");
     if (!aligned(ws, 256)) return fail(CBVH_E_INVALID, "workspace not 256-byte aligned");
-    WsPlan plan = plan_workspace(a->hdr.K, mode, n, pair_cap);
+    WsPlan plan = plan_workspace(a->hdr.K, mode, n, pair_cap, item_cap_max);
     if (ws_bytes < plan.total) return fail(CBVH_E_CAPACITY, "workspace too small");
     uint8_t *w = (uint8_t *)ws;
     cbvh::QueryArgs q;
@@ -188,6 +192,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.status = status;
     q.pair_cap = pair_cap;
     q.no_split = (flags & CBVH_NO_SPLIT) ? 1u : 0u;
+    q.wait_limit = g_wait_ticks.load();
     q.ws.hdr = (cbvh::WsHeader *)(w + plan.hdr);
     q.ws.wave_ctr = (unsigned long long *)(w + plan.wave_ctr);
     q.ws.items = (uint32_t *)(w + plan.items);
@@ -484,6 +489,13 @@ cbvh_status cbvh_set_stack_limits(uint32_t entries, uint32_t records)
     if ((entries && entries < 72) || (records && records < 20)) return fail(CBVH_E_INVALID, "limit too small");
     g_limit_entries.store(entries);
     g_limit_records.store(records);
+    return CBVH_OK;
+}
+
+cbvh_status cbvh_set_wait_limit(uint64_t ticks)
+{
+    if (ticks > 100ull * kDefaultWaitTicks) return fail(CBVH_E_INVALID, "wait limit above 1000 s");
+    g_wait_ticks.store(ticks ? ticks : kDefaultWaitTicks);
     return CBVH_OK;
 }
 

@@ -109,7 +109,7 @@ __device__ inline bool tri_tri_f64(const V3<double> *a, const V3<double> *b)
 }
 
 // squared distance from p to triangle t (Voronoi-region classification by
-// barycentric sign tests)
+// barycentric sign tests; Ericson, Real-Time Collision Detection, 5.1.5)
 template <typename T>
 __device__ inline T pt_tri_dist2(V3<T> p, const V3<T> *t)
 {
@@ -145,6 +145,7 @@ __device__ inline T pt_tri_dist2(V3<T> p, const V3<T> *t)
 
 // squared distance between segments p1-q1 and p2-q2: stationary point of
 // the convex quadratic, clamped, then the other parameter re-solved
+// (Ericson, Real-Time Collision Detection, 5.1.9)
 template <typename T>
 __device__ inline T seg_seg_dist2(V3<T> p1, V3<T> q1, V3<T> p2, V3<T> q2)
 {

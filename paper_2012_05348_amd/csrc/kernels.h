@@ -53,7 +53,7 @@ constexpr uint32_t kMaxWaves = 8192;
 struct WsHeader {
     uint32_t pose_next;   // persistent-wave pose queue
     uint32_t pair_count;  // pairs appended (may exceed capacity)
-    uint32_t error;       // a wave gave up waiting for an item (never expected)
+    uint32_t error;       // a wave gave up waiting for an item: every pose is then flagged incomplete
     uint32_t fix_count;   // leaf pairs handed to the FP64 stage (may exceed capacity)
     uint32_t n_waves;     // waves of the traversal launch (rows of per-wave counters)
     uint32_t pad0[27];
@@ -116,6 +116,7 @@ struct QueryArgs {
     uint32_t donate_min_top;    // a unit feeds waiting waves only with at least this many entries
     uint32_t max_donate;        // entries one look at the item queue may hand over
     uint32_t prio_steps;        // a unit's issue priority rises by one every this many steps (0: never)
+    unsigned long long wait_limit;  // 100 MHz ticks a waiting wave waits for an item before it gives up
     Workspace ws;
 };
 

@@ -2,8 +2,7 @@
 // Tan, Weller, Zachmann, "Compressed Bounding Volume Hierarchies for
 // Collision Detection & Proximity Query"), one wavefront per pose.
 //
-// Per wave, in LDS (or, for the rare poses that overflow it, in a large
-// per-wave slice of global memory):
+// Per wave, in LDS:
 //   records  decoded BVs (topology word + 2K float bounds) grouped in LIFO
 //            frames; a frame holds the children decoded by one node step
 //            and is the predictor for the next level's codes;
@@ -18,6 +17,11 @@
 // distance lower bound), and compact the survivors with ballot + mbcnt into
 // the entry stack (inner pairs) or the leaf queue (leaf pairs).
 // Leaf step: up to 64 triangle pairs, one per lane (checkPrimitives).
+//
+// A pose whose next node step would not fit its LDS state hands all of its
+// pending pairs to the device-wide item queue (other waves finish them);
+// if the queue cannot take them (helpers have left, or it is full) the pose
+// is flagged CBVH_POSE_STACK_OVERFLOW.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -108,7 +112,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t)
 // per-wave state layout (identical on host and device)
 // ---------------------------------------------------------------------------
 struct Layout {
-    uint32_t xf, meta, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, scratch, total;
+    uint32_t xf, meta, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, lscan, total;
 };
 
 __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
@@ -131,7 +135,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
     L.lq_lb = mode == MODE_DIST ? take(4 * lim.leafq) : o;
-    L.scratch = take(4 * WAVE);
+    L.lscan = take(4 * WAVE);
     L.total = o;
     return L;
 }
@@ -440,9 +444,6 @@ __device__ __forceinline__ unsigned long long poll64(unsigned long long *p)
 // memory clobber keeps the compiler from moving memory operations across.
 __device__ __forceinline__ void wait_mem(uint32_t dep) { asm volatile("s_waitcnt vmcnt(0)" : : "v"(dep) : "memory"); }
 
-// a waiting wave gives up (and flags the query) after this many 100 MHz
-// ticks without an item or the end of the query: 10 s, far beyond any query
-constexpr unsigned long long kWaitLimit = 1000000000ull;
 // node steps between two looks at the queue (for waiting waves to feed;
 // distance queries look less often, below)
 constexpr uint32_t kDonatePeriod = 8;
@@ -496,7 +497,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     float *ent_lb = (float *)(base + LY.ent_lb);
     uint2 *lq = (uint2 *)(base + LY.lq);
     float *lq_lb = (float *)(base + LY.lq_lb);
-    uint32_t *scratch = (uint32_t *)(base + LY.scratch);
+    uint32_t *lscan = (uint32_t *)(base + LY.lscan);  // leaf step: prefix sums of the taken leaf pairs
     uint32_t *meta = (uint32_t *)(base + LY.meta);
 
     constexpr uint32_t IW = words_of_item(K);
@@ -644,7 +645,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     }
                     if (uni(again) == 0) break;
                 }
-                if (wall_clock64() - t0 > kWaitLimit) {
+                if (wall_clock64() - t0 > q.wait_limit) {
                     if (lane == 0) {
                         rmw_xchg(&hdr->error, 1u);
                         rmw_xchg(&hdr->gone, 1u);
@@ -1015,7 +1016,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 uint64_t m_take = __ballot(lane < n_avail && incl <= (screen ? kScreenMax : (uint32_t)WAVE));
                 uint32_t n_take = __popcll(m_take);
                 uint32_t total = n_take ? lane_of(incl, (int)n_take - 1) : 0u;
-                if (lane < n_take) scratch[lane] = incl;
+                if (lane < n_take) lscan[lane] = incl;
                 wave_sync();
                 const uint32_t lq_old = lq_count;
                 lq_count -= n_take;
@@ -1025,9 +1026,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     uint32_t lo = 0, hi = n_take - 1;
                     while (lo < hi) {
                         uint32_t mid = (lo + hi) >> 1;
-                        if (scratch[mid] > t) hi = mid; else lo = mid + 1;
+                        if (lscan[mid] > t) hi = mid; else lo = mid + 1;
                     }
-                    uint32_t excl = lo ? scratch[lo - 1] : 0u;
+                    uint32_t excl = lo ? lscan[lo - 1] : 0u;
                     uint2 le = lq[lq_old - 1 - lo];
                     uint32_t local = t - excl, nb = topo_count(le.y);
                     uint32_t ia = (local * recip16(nb)) >> 16, ib = local - ia * nb;
@@ -1495,6 +1496,15 @@ __global__ __launch_bounds__(256) void fix_kernel(QueryArgs q)
     }
 }
 
+// After a wave gave up waiting for an item (the wait limit), work handed to
+// the queue may never have run: every pose of the query is flagged
+// CBVH_POSE_INCOMPLETE unless it already carries a failure of its own.
+__global__ void incomplete_kernel(const WsHeader *hdr, uint8_t *status, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && hdr->error && status[i] == 0) status[i] = 5;  // CBVH_POSE_INCOMPLETE
+}
+
 __global__ void dist_out_kernel(const unsigned long long *best64, float *dist, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1783,6 +1793,7 @@ hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t 
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(incomplete_kernel, dim3((n + 255) / 256), dim3(256), 0, s, q.ws.hdr, q.status, n);
     if (dist) {
         hipLaunchKernelGGL(dist_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, q.ws.best64, q.dist, n);
     } else if (pairs) {

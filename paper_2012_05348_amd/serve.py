@@ -21,8 +21,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (EARLY_EXIT, Model, Obstacles, cbvh_collide_batch, cbvh_distance_batch, cbvh_workspace_bytes,
-               _aligned_empty)
+from . import (EARLY_EXIT, POSE_INCOMPLETE, Model, Obstacles, cbvh_collide_batch, cbvh_distance_batch,
+               cbvh_workspace_bytes, _aligned_empty)
 
 COLLIDE, DISTANCE = 0, 1
 
@@ -181,6 +181,12 @@ class Server:
                 if s.busy is not None and s.event.query():
                     t_done = time.perf_counter() - t0
                     out_np, st_np = s.hout.numpy(), s.hstatus.numpy()
+                    n_done = sum(c for _, _, c in s.busy)
+                    if (st_np[:n_done] == POSE_INCOMPLETE).any():
+                        # a wavefront gave up waiting for handed-over work: this
+                        # launch's answers cannot be trusted
+                        raise RuntimeError("a launch gave up waiting for handed-over work (device wait limit); "
+                                           f"results of its {len(s.busy)} requests are incomplete")
                     for r, off, c in s.busy:
                         sl = slice(req.first[r], req.first[r] + c)
                         (hit if s.kind == COLLIDE else dist)[sl] = out_np[off:off + c]

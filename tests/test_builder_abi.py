@@ -254,3 +254,10 @@ def test_every_declared_function_is_exported():
     L = C.CDLL(cb.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
+
+
+def test_wait_limit_argument_is_validated():
+    with pytest.raises(cb.CbvhError):
+        cb.cbvh_set_wait_limit(10 ** 12)
+    cb.cbvh_set_wait_limit(5)
+    cb.cbvh_set_wait_limit(0)

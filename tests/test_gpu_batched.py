@@ -1,8 +1,12 @@
 """GPU tests of batched queries: one moving link against many obstacles of
-uneven size in one launch (reduced size of the batched workload).
+uneven size in one launch.
 
-The batched answers must equal the plain per-obstacle queries exactly (the
-plain kernel is the reference) and match the oracle on a sample of poses."""
+At reduced size (8 obstacles) the batched answers must equal the plain
+per-obstacle queries exactly (the plain kernel is the reference).  At the
+batched workload's full size (the 20k-triangle link against all 64
+obstacles, 30,723 poses) the booleans must equal the oracle's on every pose
+the margin accepts, and distances against an obstacle set that adds two
+200k-triangle obstacles must match the oracle within 1e-5 relative."""
 import os
 import sys
 
@@ -164,3 +168,89 @@ def test_autotuner_keeps_answers_and_picks_a_candidate(setup):
     best = res["best"]
     assert best is not None and best["ms"] == min(r["ms"] for r in res["results"])
     assert "CBVH_WAVES_PER_CU" not in os.environ
+
+
+# ---------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def full():
+    w = configs.BATCHED
+    kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    _log(f"full batched workload: building {w.n_obstacles} obstacle models")
+    link_mesh = w.link_mesh()
+    obs_meshes = [w.obstacle_mesh(i) for i in range(w.n_obstacles)]
+    link = cb.Model.build(*link_mesh, **kw).to(DEV)
+    obs = [cb.Model.build(V, T, **kw).to(DEV) for V, T in obs_meshes]
+    P, obj = w.raw_poses()
+    A = oracle.Mesh(*link_mesh)
+    return w, link_mesh, obs_meshes, link, obs, P, obj, A
+
+
+def _margin(w, link_mesh, Vb):
+    return w.margin_rel * max(meshes.mesh_diameter(link_mesh[0]), meshes.mesh_diameter(Vb))
+
+
+def test_full_batched_booleans_match_oracle_on_every_pose(full):
+    w, link_mesh, obs_meshes, link, obs, P, obj, A = full
+    oset = cb.Obstacles(obs, DEV)
+    _log(f"full batched collide: {len(P)} poses")
+    hit, st = cb.collide_batch(link, oset, torch.from_numpy(P).to(DEV), torch.from_numpy(obj).to(DEV))
+    hit, st = hit.cpu().numpy().astype(bool), st.cpu().numpy()
+    assert (st == 0).all()
+    checked = 0
+    for k, (Vb, Tb) in enumerate(obs_meshes):
+        idx = np.nonzero(obj == k)[0]
+        if len(idx) == 0:
+            continue
+        B = oracle.Mesh(Vb, Tb)
+        cls = oracle.classify_batch(A, B, P[idx], _margin(w, link_mesh, Vb))
+        keep = idx[cls != oracle.MARGINAL]
+        ref, _ = oracle.collide_batch(A, B, P[keep])
+        bad = np.nonzero(hit[keep] != ref)[0]
+        assert len(bad) == 0, (k, keep[bad[:10]])
+        checked += len(keep)
+    assert checked > len(P) - 64
+    assert 0 < hit.sum() < len(P)
+
+
+def test_batched_distances_with_200k_obstacles_match_oracle(full):
+    """The 64 obstacles plus a 200k-triangle torus and a 200k-triangle
+    icosphere: per obstacle the first 6 of its poses, and 64 poses each for
+    the two large ones; batched distances equal the plain per-obstacle
+    queries bitwise and the oracle's within 1e-5 relative (0 where they
+    collide)."""
+    w, link_mesh, obs_meshes, link, obs, P, obj, A = full
+    rng = np.random.default_rng(200000)
+    big = [meshes.torus(500, 200, 1.0, 0.3, 0.02, rng), meshes.icosphere(100, 0.1, rng)]
+    assert [len(T) for _, T in big] == [200000, 200000]
+    kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    all_meshes = obs_meshes + big
+    models = obs + [cb.Model.build(V, T, **kw).to(DEV) for V, T in big]
+    sel = np.concatenate([np.nonzero(obj == k)[0][:6] for k in range(len(obs))])
+    from synth import poses as sp
+    n_big = 64
+    Pb = sp.compose(sp.uniform_rotations(2 * n_big, rng), sp.box_translations(2 * n_big, 2.5, rng))
+    Pq = np.concatenate([P[sel], Pb])
+    oq = np.concatenate([obj[sel], np.repeat(np.arange(len(obs), len(obs) + 2, dtype=np.uint32), n_big)])
+    _log(f"batched distances: {len(Pq)} poses over {len(models)} obstacles (two of 200k triangles)")
+    oset = cb.Obstacles(models, DEV)
+    d, st = cb.distance_batch(link, oset, torch.from_numpy(Pq).to(DEV), torch.from_numpy(oq).to(DEV))
+    d, st = d.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all()
+    plain = _plain(link, models, Pq, oq, "distance")
+    assert np.array_equal(d.view(np.uint32), plain.view(np.uint32))
+    n_sep = 0
+    for k, (Vb, Tb) in enumerate(all_meshes):
+        idx = np.nonzero(oq == k)[0]
+        if len(idx) == 0:
+            continue
+        B = oracle.Mesh(Vb, Tb)
+        cls = oracle.classify_batch(A, B, Pq[idx], _margin(w, link_mesh, Vb))
+        ref, _ = oracle.distance_batch(A, B, Pq[idx])
+        sep, col = cls == oracle.SEPARATED, cls == oracle.COLLIDING
+        got = d[idx].astype(np.float64)
+        if sep.any():
+            rel = np.abs(got[sep] - ref[sep]) / ref[sep]
+            assert rel.max() <= 1e-5, (k, rel.max(), idx[sep][np.argmax(rel)])
+        assert (got[col] == 0).all(), k
+        n_sep += int(sep.sum())
+    assert n_sep > 300

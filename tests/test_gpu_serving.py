@@ -1,5 +1,8 @@
 """GPU tests of the continuous-batching serving loop: every request's result
-is the same alone and in the mix (booleans exactly, distances bitwise)."""
+is the same alone and in the mix (booleans exactly, distances bitwise), and
+at the serving workload's scale (requests of up to 4,096 poses, a
+200k-triangle obstacle) a margin-filtered sample of every request's poses
+matches the oracle."""
 import sys
 
 import numpy as np
@@ -9,9 +12,10 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
 import paper_2012_05348_amd as cb  # noqa: E402
 from paper_2012_05348_amd import serve  # noqa: E402
-from synth import configs  # noqa: E402
+from synth import configs, meshes  # noqa: E402
 
 DEV = "cuda:0"
 SMALL = configs.BatchedWorkload(index=4, n_obstacles=6, tri_max=20000, min_poses=0)
@@ -66,8 +70,90 @@ def test_results_are_the_same_alone_and_in_the_mix(server, realtime):
     assert (req.kind == serve.COLLIDE).any() and (req.kind == serve.DISTANCE).any()
 
 
+def _merge(a, b):
+    return serve.Requests(np.concatenate([a.arrival, b.arrival]), np.concatenate([a.kind, b.kind]),
+                          np.concatenate([a.obstacle, b.obstacle]),
+                          np.concatenate([a.first, b.first + len(a.poses)]), np.concatenate([a.count, b.count]),
+                          np.concatenate([a.poses, b.poses]))
+
+
+def test_served_results_match_oracle_at_scale():
+    """The serving workload's link against a 200k-triangle torus and three of
+    its obstacles, behind the default two slots per kind: 40 requests of
+    log-uniform size up to 4,096 poses plus a 4,096-pose collision request and
+    a 4,096-pose distance request against the 200k-triangle obstacle.  Every
+    request's result equals its plain query run alone, and up to 24 poses of
+    every request that the margin accepts match the oracle (booleans exactly,
+    distances within 1e-5 relative, 0 where the meshes collide)."""
+    w = configs.SERVING
+    rng = np.random.default_rng(4096)
+    link_mesh = w.link_mesh()
+    obs_meshes = [meshes.torus(500, 200, 1.0, 0.3, 0.02, rng)] + [w.obstacle_mesh(i) for i in range(3)]
+    assert len(obs_meshes[0][1]) == 200000
+    kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    link = cb.Model.build(*link_mesh, **kw).to(DEV)
+    obs = [cb.Model.build(V, T, **kw).to(DEV) for V, T in obs_meshes]
+    srv = serve.Server(link, cb.Obstacles(obs, DEV), DEV)
+    big = serve.make_requests(2, np.inf, 1, rng, batch_min=4096, batch_max=4096)
+    big.kind[:] = [serve.COLLIDE, serve.DISTANCE]
+    req = _merge(serve.make_requests(40, np.inf, len(obs), rng, batch_max=4096), big)
+    _log(f"serving at scale: {len(req)} requests, {len(req.poses)} poses, largest {int(req.count.max())}")
+    res = srv.run(req, realtime=False)
+    assert (res["status"] == 0).all()
+    A = oracle.Mesh(*link_mesh)
+    Bs = [oracle.Mesh(V, T) for V, T in obs_meshes]
+    checked = {serve.COLLIDE: 0, serve.DISTANCE: 0}
+    for r in range(len(req)):
+        sl = slice(req.first[r], req.first[r] + req.count[r])
+        got = res["hit"][sl] if req.kind[r] == serve.COLLIDE else res["dist"][sl]
+        ref, st = _alone(link, obs, req, r)
+        assert (st == 0).all()
+        assert np.array_equal(np.asarray(got).view(np.uint8 if req.kind[r] == serve.COLLIDE else np.uint32),
+                              ref.view(np.uint8 if req.kind[r] == serve.COLLIDE else np.uint32)), r
+        k = int(req.obstacle[r])
+        idx = np.sort(rng.choice(int(req.count[r]), min(24, int(req.count[r])), replace=False))
+        Pq = req.poses[sl][idx]
+        m = w.margin_rel * max(meshes.mesh_diameter(link_mesh[0]), meshes.mesh_diameter(obs_meshes[k][0]))
+        cls = oracle.classify_batch(A, Bs[k], Pq, m)
+        sep, col = cls == oracle.SEPARATED, cls == oracle.COLLIDING
+        if req.kind[r] == serve.COLLIDE:
+            keep = sep | col
+            ref_h, _ = oracle.collide_batch(A, Bs[k], Pq[keep])
+            assert np.array_equal(got[idx][keep].astype(bool), ref_h), r
+            checked[serve.COLLIDE] += int(keep.sum())
+        else:
+            ref_d, _ = oracle.distance_batch(A, Bs[k], Pq)
+            g = got[idx].astype(np.float64)
+            if sep.any():
+                assert (np.abs(g[sep] - ref_d[sep]) / ref_d[sep]).max() <= 1e-5, r
+            assert (g[col] == 0).all(), r
+            checked[serve.DISTANCE] += int((sep | col).sum())
+    _log(f"serving at scale: oracle checked {checked}")
+    assert checked[serve.COLLIDE] > 200 and checked[serve.DISTANCE] > 60
+
+
 def test_a_request_larger_than_a_launch_is_rejected(server):
     _, obs, srv = server
     req = serve.make_requests(3, np.inf, len(obs), np.random.default_rng(3), batch_min=700, batch_max=800)
     with pytest.raises(ValueError):
         srv.run(req, realtime=False)
+
+
+def test_an_incomplete_launch_fails_the_run(server):
+    """With a device wait limit of one tick every launch gives up waiting for
+    handed-over work and flags its poses incomplete; the loop raises instead
+    of returning those answers.  A fresh server (the raise leaves launches
+    in flight) runs normally once the default limit is back."""
+    link, obs, _ = server
+    srv = serve.Server(link, cb.Obstacles(obs, DEV), DEV, slots_per_kind=1, max_poses=600)
+    req = serve.make_requests(8, np.inf, len(obs), np.random.default_rng(21), batch_max=300)
+    try:
+        cb.cbvh_set_wait_limit(1)
+        with pytest.raises(RuntimeError, match="wait limit"):
+            srv.run(req, realtime=False)
+        torch.cuda.synchronize()
+    finally:
+        cb.cbvh_set_wait_limit(0)
+    srv2 = serve.Server(link, cb.Obstacles(obs, DEV), DEV, slots_per_kind=1, max_poses=600)
+    res = srv2.run(req, realtime=False)
+    assert (res["status"] == 0).all()

@@ -41,7 +41,3 @@ def config0_poses():
     idx = np.sort(np.concatenate([col, sep]))
     return raw[idx], int(np.count_nonzero(cls[: idx[-1] + 1] == oracle.MARGINAL))
 
-
-def sample_indices(n, k, seed=0):
-    rng = np.random.default_rng(seed)
-    return np.sort(rng.choice(n, size=min(k, n), replace=False))
