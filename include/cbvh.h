@@ -174,6 +174,22 @@ cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_mod
                           const float *poses, uint32_t n, uint32_t flags, float *dist, uint8_t *pose_status,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): collision
+ * booleans as cbvh_collide with CBVH_EARLY_EXIT (flags: CBVH_EARLY_EXIT,
+ * CBVH_NO_SPLIT), but with no workspace argument.  The workspace is a fixed
+ * device array of 32 MiB inside the library, one per GPU, held until the
+ * process ends; this call allocates nothing (no hipMalloc, no library
+ * allocation).  n <= CBVH_STATIC_MAX_POSES, else CBVH_E_CAPACITY before
+ * anything is enqueued.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents (each call clears what must start at zero):
+ * calls that overlap in time on one GPU race and must not be made (serialize
+ * them, e.g. on one stream).  The caller still passes inputs and outputs. */
+#define CBVH_STATIC_MAX_POSES 262144u
+cbvh_status cbvh_collide_static(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                                const float *poses, uint32_t n, uint32_t flags, uint8_t *hit, uint8_t *pose_status,
+                                void *stream);
+
 /* ---- batched queries: many fixed models ("obstacles") in one launch ----
  *
  * The batched form of the queries above (section I's use case: test

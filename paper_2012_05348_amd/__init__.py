@@ -77,6 +77,7 @@ def lib():
             "cbvh_workspace_bytes": (sz, [P, P, u32, u32, u32]),
             "cbvh_collide": (st, [P, P, P, P, P, u32, u32, P, P, u32, P, P, P, sz, P]),
             "cbvh_distance": (st, [P, P, P, P, P, u32, u32, P, P, P, sz, P]),
+            "cbvh_collide_static": (st, [P, P, P, P, P, u32, u32, P, P, P]),
             "cbvh_obstacles_device_bytes": (sz, [u32]),
             "cbvh_obstacles_create": (st, [C.POINTER(P), C.POINTER(P), u32, P, sz, P, C.POINTER(P)]),
             "cbvh_obstacles_free": (None, [P]),
@@ -178,6 +179,14 @@ def cbvh_collide(a, a_dev, b, b_dev, poses, n, flags, hit, pairs, pair_capacity,
 def cbvh_distance(a, a_dev, b, b_dev, poses, n, flags, dist, pose_status, workspace, stream=None):
     _check(lib().cbvh_distance(a, _ptr(a_dev), b, _ptr(b_dev), _ptr(poses), n, flags, _ptr(dist), _ptr(pose_status),
                                _ptr(workspace), 0 if workspace is None else workspace.numel(), _stream(stream)))
+
+
+STATIC_MAX_POSES = 262144  # CBVH_STATIC_MAX_POSES
+
+
+def cbvh_collide_static(a, a_dev, b, b_dev, poses, n, flags, hit, pose_status, stream=None):
+    _check(lib().cbvh_collide_static(a, _ptr(a_dev), b, _ptr(b_dev), _ptr(poses), n, flags, _ptr(hit),
+                                     _ptr(pose_status), _stream(stream)))
 
 
 def cbvh_obstacles_device_bytes(n) -> int:

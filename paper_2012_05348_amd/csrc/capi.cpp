@@ -39,6 +39,8 @@ cbvh_status fail_hip(hipError_t e, const char *what)
 }
 
 std::atomic<uint32_t> g_limit_entries{0}, g_limit_records{0};
+// fewest item-queue slots the allocation-free entry point accepts
+constexpr uint64_t kStaticMinItems = 65536;
 // how long a waiting wave waits for a work item before it gives up and the
 // query's poses are flagged incomplete: 10 s of the 100 MHz device clock
 constexpr uint64_t kDefaultWaitTicks = 1000000000ull;
@@ -353,6 +355,30 @@ cbvh_status cbvh_distance(const cbvh_model *a, const void *a_dev, const cbvh_mod
     if (flags & ~CBVH_NO_SPLIT) return fail(CBVH_E_INVALID, "unknown flag");
     return run_query(a, a_dev, b, b_dev, poses, n, cbvh::MODE_DIST, flags, nullptr, dist, nullptr, 0, nullptr,
                      pose_status, workspace, workspace_bytes, stream);
+}
+
+cbvh_status cbvh_collide_static(const cbvh_model *a, const void *a_dev, const cbvh_model *b, const void *b_dev,
+                                const float *poses, uint32_t n, uint32_t flags, uint8_t *hit, uint8_t *pose_status,
+                                void *stream)
+{
+    if (flags & ~(CBVH_EARLY_EXIT | CBVH_NO_SPLIT)) return fail(CBVH_E_INVALID, "unknown or unsupported flag");
+    if (n > CBVH_STATIC_MAX_POSES)
+        return fail(CBVH_E_CAPACITY, "more than " + std::to_string(CBVH_STATIC_MAX_POSES) +
+                                         " poses for the fixed workspace of cbvh_collide_static");
+    if (!a || !b) return fail(CBVH_E_INVALID, "model is NULL");
+    if (n == 0) return check_pair(a, a_dev, b, b_dev);
+    // the item queue takes whatever the fixed array leaves after the rest of
+    // the workspace (the donation path refuses items beyond it)
+    const WsPlan fixed = plan_workspace(a->hdr.K, cbvh::MODE_BOOL, n, 0, 0);
+    const uint64_t per_item = 4ull * cbvh::item_words(a->hdr.K) + 4ull, slack = 1024;
+    if (fixed.total + slack + per_item * kStaticMinItems > cbvh::kStaticWorkspaceBytes)
+        return fail(CBVH_E_CAPACITY, "the fixed workspace of cbvh_collide_static is too small for this batch");
+    const uint64_t cap = (cbvh::kStaticWorkspaceBytes - fixed.total - slack) / per_item;
+    void *ws = nullptr;
+    hipError_t e = cbvh::static_workspace(&ws);
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress");
+    return run_query(a, a_dev, b, b_dev, poses, n, cbvh::MODE_BOOL, flags, hit, nullptr, nullptr, 0, nullptr,
+                     pose_status, ws, cbvh::kStaticWorkspaceBytes, stream, nullptr, nullptr, cap);
 }
 
 size_t cbvh_obstacles_device_bytes(uint32_t n) { return (size_t)align_up((uint64_t)n * sizeof(cbvh::DevModel), 256); }

@@ -132,4 +132,12 @@ hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t 
 
 hipError_t launch_decode_all(const DevModel &m, float *out, hipStream_t stream);
 
+// The allocation-free query entry point's workspace: a fixed device array of
+// this many bytes per GPU (held until the process ends), shared by every
+// such call on that GPU.
+constexpr size_t kStaticWorkspaceBytes = 32ull << 20;
+constexpr int kMaxDevices = 64;
+// Device address of the current device's array (looked up once per device).
+hipError_t static_workspace(void **out);
+
 }  // namespace cbvh

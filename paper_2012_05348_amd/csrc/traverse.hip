@@ -27,6 +27,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <mutex>
+
 #include "format.h"
 #include "geom.h"
 #include "kernels.h"
@@ -1760,6 +1762,31 @@ hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 }
 
 }  // namespace
+
+// Workspace of the allocation-free query entry point: a fixed device array
+// that every call on a GPU shares (each GPU holds its own copy).  Host code
+// never uses the array's name as an address: its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+hipError_t static_workspace(void **out)
+{
+    static std::mutex mu;
+    static void *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return make_layout(K, mode, lim).total; }
 
