@@ -327,34 +327,6 @@ __device__ __forceinline__ void load_tri(const float *tris, uint32_t i, V3<float
         t[v] = {gload<float>(p + 3 * v), gload<float>(p + 3 * v + 1), gload<float>(p + 3 * v + 2)};
 }
 
-struct Pose {
-    float R[9], t[3];
-};
-
-__device__ __forceinline__ V3<float> xform_f32(const Pose &P, V3<float> x)
-{
-    return {__builtin_fmaf(P.R[0], x.x, __builtin_fmaf(P.R[1], x.y, __builtin_fmaf(P.R[2], x.z, P.t[0]))),
-            __builtin_fmaf(P.R[3], x.x, __builtin_fmaf(P.R[4], x.y, __builtin_fmaf(P.R[5], x.z, P.t[1]))),
-            __builtin_fmaf(P.R[6], x.x, __builtin_fmaf(P.R[7], x.y, __builtin_fmaf(P.R[8], x.z, P.t[2])))};
-}
-__device__ __forceinline__ V3<double> xform_f64(const Pose &P, V3<float> x)
-{
-    double X = x.x, Y = x.y, Z = x.z;
-    return {fma((double)P.R[0], X, fma((double)P.R[1], Y, fma((double)P.R[2], Z, (double)P.t[0]))),
-            fma((double)P.R[3], X, fma((double)P.R[4], Y, fma((double)P.R[5], Z, (double)P.t[1]))),
-            fma((double)P.R[6], X, fma((double)P.R[7], Y, fma((double)P.R[8], Z, (double)P.t[2])))};
-}
-__device__ __forceinline__ V3<double> to64(V3<float> x) { return {(double)x.x, (double)x.y, (double)x.z}; }
-
-// Distance queries: bound on the error of an FP32 leaf distance (a generous
-// multiple of the transform and closest-point rounding at this coordinate
-// scale).  The traversal and the FP64 stage evaluate it identically.
-__device__ __forceinline__ float dist_err_abs(const float *pose, float maxA, float maxB)
-{
-    const float tx = pose[3], ty = pose[7], tz = pose[11];
-    const float tnorm = sqrtf(tx * tx + ty * ty + tz * tz);
-    return 256.0f * 0x1p-24f * (tnorm + 3.5f * (maxA + maxB));
-}
 
 // Lower bound on the distance between A's box placed by the pose and B's
 // axis-aligned box: their gap along one direction n, from a point of A's
@@ -1102,17 +1074,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                             // it is accurate if they are disjoint and too large
                             // (never too small) if they intersect, so the running
                             // bound stays safe; the FP64 stage decides them
-                            float d32 = 0.0f;
-                            if (res != 1) {
-                                V3<float> ar[3], br[3];
-#pragma unroll
-                                for (int v = 0; v < 3; v++) {
-                                    ar[v] = vsub(a[v], a[0]);
-                                    br[v] = vsub(b[v], a[0]);
-                                }
-                                d32 = sqrtf(tri_tri_dist2(ar, br));
-                            }
-                            dres = d32;
+                            dres = res != 1 ? tri_dist_f32(a, b) : 0.0f;
                         }
                     }
                     cnt.tri_tests += n_pass;
