@@ -164,6 +164,39 @@ def summarize(r, steps):
     }
 
 
+def run_treelet_sweep(cb, w, dev, sizes, calls=10):
+    """The scaled workload's models built with treelets of each size (bytes;
+    the largest holds the whole tree): descriptor bytes, absolute treelet
+    tops, traversal kernel time, answers against the first size."""
+    import torch
+    from paper_2012_05348_amd import autotune
+    (va, ta), (vb, tb) = w.meshes()
+    P = torch.from_numpy(w.raw_poses()).to(dev)
+    n = P.shape[0]
+    out, ref = [], None
+    for tb_ in sizes:
+        progress(f"treelet sweep: {tb_} bytes")
+        kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits, treelet_bytes=tb_)
+        ma, mb = cb.Model.build(va, ta, **kw).to(dev), cb.Model.build(vb, tb, **kw).to(dev)
+        ws = cb.workspace(ma, mb, n, cb.EARLY_EXIT, 0, dev)
+        hit = torch.empty(n, dtype=torch.uint8, device=dev)
+        st = torch.empty(n, dtype=torch.uint8, device=dev)
+
+        def step():
+            cb.cbvh_collide(ma.handle, ma.dev, mb.handle, mb.dev, P, n, cb.EARLY_EXIT, hit, None, 0, None, st, ws.buf)
+
+        traversal_kernel_ms(cb, step, ws.buf, 3)
+        k = traversal_kernel_ms(cb, step, ws.buf, calls)
+        h = hit.cpu().numpy()
+        ref = h if ref is None else ref
+        info = ma.info()
+        out.append({"treelet_bytes": "whole tree" if tb_ == autotune.WHOLE_TREE else tb_,
+                    "treelets": info["n_treelets"], "absolute_nodes": info["n_abs"],
+                    "descriptor_bytes": info["descriptor_bytes"], "kernel_ms_median": float(np.median(k)),
+                    "hits_equal": bool(np.array_equal(h, ref)), "status_ok": bool((st == 0).all().item())})
+    return out
+
+
 def run_batched(cb, dev, steps, warmup):
     """The batched workload: a 20k-triangle link against 64 obstacles of uneven
     size (1k-200k triangles) in one launch, against the plain kernel run once
@@ -223,13 +256,35 @@ def run_batched(cb, dev, steps, warmup):
     graph_equal = bool(torch.equal(hit, hits))
     progress(f"  batched {np.mean(dev_ms):.3f} ms, plain x{len(groups)} {np.mean(pdev_ms):.3f} ms, "
              f"graph {np.mean(gdev_ms):.3f} ms")
-    # autotuner over branching factor and waves per CU (answers must not change)
+    # autotuner over branching factor, treelet size (2, 8, 32 KiB and one
+    # treelet for the whole tree), waves per CU and waves per workgroup
+    # (answers must not change); the pick is stored, then applied: models
+    # rebuilt with its build parameters, launches with its launch knobs
     from paper_2012_05348_amd import autotune
-    progress("batched: autotune (branching 4/8, waves per CU as many as fit / 8)")
+    progress("batched: autotune (branching 4/8, treelets 2/8/32 KiB and whole tree, waves per CU, per workgroup)")
     tuned = autotune.tune(link_mesh, obs_meshes, P, obj, bits=w.bits, leaf_size=w.leaf_size, branchings=(4, 8),
-                          treelet_bytes=(8192,), waves_per_cu=(0, 8), steps=5, warmup=2, device=dev)
+                          treelet_bytes=(2048, 8192, 32768, autotune.WHOLE_TREE), waves_per_cu=(0, 8),
+                          waves_per_group=(1, 2, 4), steps=5, warmup=2, device=dev)
+    applied = None
+    if tuned["best"]:
+        cache = autotune.save(w.name, tuned["best"])
+        cfg = autotune.load(w.name)
+        kw_t = dict(bv=cb.DOP18, leaf_size=w.leaf_size, bits=w.bits, **autotune.build_kwargs(cfg))
+        link_t = cb.Model.build(*link_mesh, **kw_t).to(dev)
+        oset_t = cb.Obstacles([cb.Model.build(*m, **kw_t).to(dev) for m in obs_meshes], dev)
+        hit_t = torch.empty(n, dtype=torch.uint8, device=dev)
+
+        def tuned_step():
+            cb.cbvh_collide_batch(link_t.handle, link_t.dev, oset_t.handle, Pd, od, n, cb.EARLY_EXIT, hit_t, st, ws.buf)
+
+        with autotune.launch_env(cfg):
+            twall, tdev_ms = time_steps(tuned_step, steps, warmup)
+        applied = {"config": cfg, "cache": cache, "poses_per_sec": n * steps / twall,
+                   "ms_per_call_median": float(np.median(tdev_ms)), "hits_equal": bool(torch.equal(hit_t, hits)),
+                   "status_ok": bool((st == 0).all().item())}
+        progress(f"  tuned pick {cfg}: {applied['ms_per_call_median']:.3f} ms")
     return {
-        "autotune": tuned,
+        "autotune": tuned, "tuned_applied": applied,
         "workload": w.name, "poses": n, "batches": len(w.batches()), "obstacles": w.n_obstacles,
         "obstacle_triangles": int(sum(s_.n_tris for s_ in w.obstacle_specs())),
         "poses_per_sec": n * steps / wall, "ms_per_call_median": float(np.median(dev_ms)),
@@ -252,17 +307,21 @@ def run_serving(cb, dev, n_requests=1500):
     from synth import configs
     w = configs.SERVING
     kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
-    progress(f"serving: building {w.n_obstacles} resident obstacle models")
+    # the batched workload's tuned pick (build parameters and launch knobs), where one is stored
+    from paper_2012_05348_amd import autotune
+    cfg = autotune.load(configs.BATCHED.name)
+    kw.update(autotune.build_kwargs(cfg, w.branching))
+    progress(f"serving: building {w.n_obstacles} resident obstacle models (tuned pick {cfg})")
     link = cb.Model.build(*w.link_mesh(), **kw).to(dev)
     oset = cb.Obstacles([cb.Model.build(*w.obstacle_mesh(i), **kw).to(dev) for i in range(w.n_obstacles)], dev)
-    srv = serve.Server(link, oset, dev)
+    srv = serve.Server(link, oset, dev, launch_cfg=cfg)
     rng = configs.rng_for(4, 2)
     warm = serve.make_requests(200, np.inf, w.n_obstacles, rng)
     srv.run(warm, realtime=False)
     sat_req = serve.make_requests(n_requests, np.inf, w.n_obstacles, rng)
     sat = srv.run(sat_req, realtime=False)
     rate = sat["requests_per_sec"]
-    out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests,
+    out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests, "tuned": cfg,
            "saturation": {k: sat[k] for k in ("poses_per_sec", "requests_per_sec", "launches", "p50_ms", "p99_ms")}}
     out["saturation"]["status_ok"] = bool((sat["status"] == 0).all())
     # each served request against its plain query run alone (the judge of the batched path)
@@ -542,6 +601,8 @@ def main():
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
             pr = run_distance(cb, w2, bits, dev, 5, 1)
             out[key] = summarize(pr, 5)
+        from paper_2012_05348_amd import autotune
+        out["treelet_sweep_scaled"] = run_treelet_sweep(cb, w, dev, (2048, 8192, 32768, autotune.WHOLE_TREE))
         out["batched"] = run_batched(cb, dev, 10, 2)
         out["serving"] = run_serving(cb, dev)
     if args.large_obstacle_set:

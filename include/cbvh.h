@@ -262,6 +262,7 @@ typedef struct {
                                 CBVH_POSE_INCOMPLETE unless flagged otherwise) */
     uint64_t node_steps;     /* node steps: one frame of children decoded and tested (up to 64 records) */
     uint64_t leaf_steps;     /* leaf steps: up to 64 triangle pairs tested */
+    uint64_t waves;          /* wavefronts of the traversal launch (resident at once when the GPU is idle) */
 } cbvh_stats_t;
 
 cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats_t *out, void *stream);

@@ -49,7 +49,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("bv_tests", "tri_tests", "tri_fp64", "expansions", "node_bytes",
                                            "tri_bytes", "donated_items", "max_entries", "max_records",
                                            "t_start", "t_drain", "t_end", "max_pose_steps", "wait_timeouts",
-                                           "node_steps", "leaf_steps")]
+                                           "node_steps", "leaf_steps", "waves")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

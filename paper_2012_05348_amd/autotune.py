@@ -1,19 +1,27 @@
 """Autotuner for batched queries: picks the build parameters (branching factor,
-treelet size) and the launch shape (waves per CU) that answer a batched
-collision workload fastest on the current GPU.
+treelet size) and the launch shape (waves per CU, waves per workgroup) that
+answer a batched collision workload fastest on the current GPU.
 
 Every candidate must give answers identical to the first one: build
 parameters and launch shape change how the work is done, never what the
 answer is, so a candidate whose answers differ is reported as a failure.
 
+The pick is kept in a cache file (``save`` / ``load``; default
+``$CBVH_TUNE_CACHE`` or ``~/.cache/cbvh/autotune.json``, one entry per GPU
+name and workload) and applied with ``build_kwargs`` (model build
+parameters) and ``launch_env`` (the launch knobs, environment variables the
+library reads at every launch).
+
     python -m paper_2012_05348_amd.autotune --out tuned.json
 
 tunes the library's batched workload (a 20k-triangle link against 64
-obstacles of 1k-200k triangles); `tune()` takes any meshes and poses.
+obstacles of 1k-200k triangles) and stores the pick in the cache; `tune()`
+takes any meshes and poses.
 """
 from __future__ import annotations
 
 import argparse
+import contextlib
 import itertools
 import json
 import os
@@ -25,6 +33,75 @@ import numpy as np
 from . import (DOP18, EARLY_EXIT, Model, Obstacles, cbvh_collide_batch, workspace)
 
 WAVES_ENV = "CBVH_WAVES_PER_CU"
+GROUP_ENV = "CBVH_WAVES_PER_GROUP"
+CACHE_ENV = "CBVH_TUNE_CACHE"
+WHOLE_TREE = 1 << 30  # a treelet budget no model reaches: one treelet holds the whole tree
+
+
+@contextlib.contextmanager
+def launch_env(cfg):
+    """Launch knobs of a tuned configuration ({"waves_per_cu", "waves_per_group"};
+    0 or missing = the library's default) set for the duration of the block;
+    cfg None leaves the environment alone."""
+    if cfg is None:
+        yield
+        return
+    saved = {k: os.environ.get(k) for k in (WAVES_ENV, GROUP_ENV)}
+    try:
+        for key, env in (("waves_per_cu", WAVES_ENV), ("waves_per_group", GROUP_ENV)):
+            v = int((cfg or {}).get(key) or 0)
+            if v:
+                os.environ[env] = str(v)
+            else:
+                os.environ.pop(env, None)
+        yield
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def build_kwargs(cfg, default_branching=8):
+    """Model build parameters of a tuned configuration."""
+    return {"branching": int((cfg or {}).get("branching") or default_branching),
+            "treelet_bytes": int((cfg or {}).get("treelet_bytes") or 0)}
+
+
+def cache_path(path=None):
+    return path or os.environ.get(CACHE_ENV) or os.path.join(os.path.expanduser("~"), ".cache", "cbvh",
+                                                              "autotune.json")
+
+
+def _gpu_name():
+    import torch
+    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+
+
+def save(workload, best, path=None):
+    """Store the pick for (this GPU, workload) in the cache file."""
+    p = cache_path(path)
+    data = {}
+    if os.path.exists(p):
+        with open(p) as f:
+            data = json.load(f)
+    data[f"{_gpu_name()}|{workload}"] = best
+    os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1)
+    os.replace(tmp, p)
+    return p
+
+
+def load(workload, path=None):
+    """The stored pick for (this GPU, workload), or None."""
+    p = cache_path(path)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        return json.load(f).get(f"{_gpu_name()}|{workload}")
 
 
 def _time_batched(link, oset, Pd, od, n, steps, warmup):
@@ -51,8 +128,8 @@ def _time_batched(link, oset, Pd, od, n, steps, warmup):
 
 
 def tune(link_mesh, obstacle_meshes, poses, pose_obstacle, bv=DOP18, bits=16, leaf_size=4,
-         branchings=(4, 8), treelet_bytes=(2048, 8192, 32768), waves_per_cu=(0, 8), steps=5, warmup=2,
-         device="cuda", log=None):
+         branchings=(4, 8), treelet_bytes=(2048, 8192, 32768, WHOLE_TREE), waves_per_cu=(0, 8),
+         waves_per_group=(1, 2, 4), steps=5, warmup=2, device="cuda", log=None):
     """Time every candidate; returns {"best": {...}, "results": [...]}.
     waves_per_cu 0 means as many as fit (the library's default)."""
     import torch
@@ -60,33 +137,23 @@ def tune(link_mesh, obstacle_meshes, poses, pose_obstacle, bv=DOP18, bits=16, le
     Pd = torch.from_numpy(np.ascontiguousarray(poses, dtype=np.float32)).to(device)
     od = torch.from_numpy(np.ascontiguousarray(pose_obstacle, dtype=np.uint32)).to(device)
     results, reference = [], None
-    saved = os.environ.get(WAVES_ENV)
-    try:
-        for bf, tb in itertools.product(branchings, treelet_bytes):
-            t0 = time.perf_counter()
-            kw = dict(bv=bv, branching=bf, leaf_size=leaf_size, bits=bits, treelet_bytes=tb)
-            link = Model.build(*link_mesh, **kw).to(device)
-            oset = Obstacles([Model.build(V, T, **kw).to(device) for V, T in obstacle_meshes], device)
-            build_s = time.perf_counter() - t0
-            for wpc in waves_per_cu:
-                if wpc:
-                    os.environ[WAVES_ENV] = str(wpc)
-                else:
-                    os.environ.pop(WAVES_ENV, None)
+    for bf, tb in itertools.product(branchings, treelet_bytes):
+        t0 = time.perf_counter()
+        kw = dict(bv=bv, branching=bf, leaf_size=leaf_size, bits=bits, treelet_bytes=tb)
+        link = Model.build(*link_mesh, **kw).to(device)
+        oset = Obstacles([Model.build(V, T, **kw).to(device) for V, T in obstacle_meshes], device)
+        build_s = time.perf_counter() - t0
+        for wpc, wpg in itertools.product(waves_per_cu, waves_per_group):
+            cfg = {"branching": bf, "treelet_bytes": tb, "waves_per_cu": wpc, "waves_per_group": wpg}
+            with launch_env(cfg):
                 ms, hit, ok = _time_batched(link, oset, Pd, od, n, steps, warmup)
-                if reference is None:
-                    reference = hit
-                same = bool(np.array_equal(hit, reference)) and ok
-                r = {"branching": bf, "treelet_bytes": tb, "waves_per_cu": wpc, "ms": ms,
-                     "poses_per_sec": n / (ms * 1e-3), "answers_equal": same, "build_s": build_s}
-                results.append(r)
-                if log:
-                    log(f"autotune {r}")
-    finally:
-        if saved is None:
-            os.environ.pop(WAVES_ENV, None)
-        else:
-            os.environ[WAVES_ENV] = saved
+            if reference is None:
+                reference = hit
+            same = bool(np.array_equal(hit, reference)) and ok
+            r = dict(cfg, ms=ms, poses_per_sec=n / (ms * 1e-3), answers_equal=same, build_s=build_s)
+            results.append(r)
+            if log:
+                log(f"autotune {r}")
     good = [r for r in results if r["answers_equal"]]
     best = min(good, key=lambda r: r["ms"]) if good else None
     return {"best": best, "results": results, "all_answers_equal": len(good) == len(results)}
@@ -96,19 +163,23 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--out", default=None, help="write the results as JSON here")
     ap.add_argument("--quick", action="store_true", help="branching {4, 8} and the default treelet size only")
+    ap.add_argument("--cache", default=None, help="cache file for the pick (default: $CBVH_TUNE_CACHE or "
+                                                  "~/.cache/cbvh/autotune.json)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from synth import configs
     w = configs.BATCHED
     P, obj = w.raw_poses()
     meshes_ = [w.obstacle_mesh(i) for i in range(w.n_obstacles)]
-    tbs = (8192,) if args.quick else (2048, 8192, 32768)
+    tbs = (8192,) if args.quick else (2048, 8192, 32768, WHOLE_TREE)
     res = tune(w.link_mesh(), meshes_, P, obj, bits=w.bits, leaf_size=w.leaf_size, treelet_bytes=tbs,
                log=lambda m: print(m, file=sys.stderr, flush=True))
     text = json.dumps(res, indent=1)
     if args.out:
         with open(args.out, "w") as f:
             f.write(text)
+    if res["best"]:
+        print("stored in", save(w.name, res["best"], args.cache), file=sys.stderr)
     print(json.dumps(res["best"]))
 
 

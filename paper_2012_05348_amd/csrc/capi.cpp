@@ -505,6 +505,7 @@ cbvh_status cbvh_stats(const void *workspace, size_t workspace_bytes, cbvh_stats
     out->max_pose_steps = c[cbvh::C_MAX_POSE_STEPS];
     out->node_steps = c[cbvh::C_NODE_STEPS];
     out->leaf_steps = c[cbvh::C_LEAF_STEPS];
+    out->waves = nw;
     return CBVH_OK;
 }
 

@@ -121,7 +121,7 @@ struct QueryArgs {
 };
 
 // Bytes of one wave's traversal state for K slabs, a mode and limits.
-size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim);
+size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim, uint32_t bits);
 StackLimits default_limits(uint32_t K, int mode);
 uint32_t item_words(uint32_t K);
 

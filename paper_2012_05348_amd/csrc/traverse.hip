@@ -37,6 +37,7 @@ namespace cbvh {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr uint32_t kMaxWavesPerGroup = 4;            // waves per workgroup (the launch's workgroup shape), most
 constexpr int PMAX = 8;                              // entries popped by one node step (most)
 constexpr uint32_t TMAX = 64;                        // child-pair tests of one node step (most): one pass
 constexpr uint32_t AMAX = 32;                        // A records of one node step (most)
@@ -113,11 +114,19 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t)
 // ---------------------------------------------------------------------------
 // per-wave state layout (identical on host and device)
 // ---------------------------------------------------------------------------
+// A record is one decoded BV: 2K bounds (lo, hi per slab), its topology word
+// and one pad word, 16-byte aligned so that it moves in 16-byte LDS accesses.
+__host__ __device__ constexpr uint32_t rec_words(uint32_t K) { return 2 * K + 2; }
+// Collision queries keep both topology words in each pending entry (one LDS
+// access pops an entry); distance queries, whose stacks are far deeper, read
+// them from the records.
+__host__ __device__ constexpr bool topo_in_entry(int mode) { return mode != MODE_DIST; }
+
 struct Layout {
-    uint32_t xf, meta, frame_end, rtopo, rbnd, ta, tsph, ent, ent_lb, lq, lq_lb, lscan, total;
+    uint32_t ctr, xf, rec, ta, ta_topo, tsph, ent, ent_tp, ent_lb, lq, lq_lb, lscan, total;
 };
 
-__host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim)
+__host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim, uint32_t bits)
 {
     Layout L;
     uint32_t o = 0;
@@ -126,14 +135,14 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
         o += (bytes + 15u) & ~15u;
         return r;
     };
+    L.ctr = take(8 * C_NUM);
     L.xf = take(32 * K);
-    L.meta = take(4 * PMAX);
-    L.frame_end = take(4 * MAX_FRAMES);
-    L.rtopo = take(4 * lim.records);
-    L.rbnd = take(8 * K * lim.records);
-    L.ta = (mode == MODE_DIST && K == 3) ? o : take(8 * K * TA_MAX);  // AABB distance tests read no transform
-    L.tsph = take(32 * TA_MAX);
+    L.rec = take(4 * rec_words(K) * lim.records);
+    L.ta = (mode == MODE_DIST && K == 3) ? o : take(4 * rec_words(K) * TA_MAX);  // AABB distance tests read no transform
+    L.ta_topo = take(4 * TA_MAX);
+    L.tsph = (mode == MODE_DIST || K == 3) ? take(32 * TA_MAX) : o;
     L.ent = take(4 * lim.entries);
+    L.ent_tp = topo_in_entry(mode) ? take(8 * lim.entries) : o;
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
     L.lq = take(8 * lim.leafq);
     L.lq_lb = mode == MODE_DIST ? take(4 * lim.leafq) : o;
@@ -255,24 +264,19 @@ struct NodeWords {
 template <int K, int BITS>
 __device__ __forceinline__ void load_node(const DevModel &M, uint32_t node, uint32_t &topo, NodeWords<K, BITS> &nw)
 {
+    topo = gload<uint32_t>(M.topo + node);
     const uint8_t *code = M.codes + (size_t)node * M.stride;
 #pragma unroll
     for (int k = 0; k < NodeWords<K, BITS>::N; k++)
         nw.w[k] = BITS == 8 ? (uint32_t)gload<uint16_t>(code + 2 * k) : gload<uint32_t>(code + 4 * k);
-    topo = gload<uint32_t>(M.topo + node);
-    // keep the compiler from sinking the code-word loads behind the branch
-    // on the topology word (which would serialise two round trips)
-#pragma unroll
-    for (int k = 0; k < NodeWords<K, BITS>::N; k++) asm volatile("" : "+v"(nw.w[k]));
 }
 
 // Decode one node's 2K bounds (lo, hi per slab) from its parent's decoded
 // bounds: E = Ph - Pl, s = E * 2^-BITS (0 if E < 2^-100), lo = fma(ql, s, Pl),
 // hi = fma(-qh, s, Ph).  Absolute nodes (treelet tops) and uncompressed
 // models read FP32 bounds instead, half-precision models binary16 bounds.
-template <int K, int BITS, typename ParentPtr>
-__device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
-                                             ParentPtr parent, float out[2 * K])
+template <int K, int BITS>
+__device__ __forceinline__ void decode_rel(const NodeWords<K, BITS> &nw, const float *parent, float out[2 * K])
 {
     if constexpr (BITS == (int)kBitsFp16) {
         // binary16 absolute bounds, widened exactly
@@ -284,16 +288,6 @@ __device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, c
     } else if constexpr (BITS == 0) {
 #pragma unroll
         for (int k = 0; k < 2 * K; k++) out[k] = __uint_as_float(nw.w[k]);
-    } else if (topo_abs(topo)) {
-        // the first four code bytes hold the node's index in the FP32 table
-        const uint32_t ai = BITS == 8 ? (nw.w[0] | (nw.w[1] << 16)) : nw.w[0];
-        const uint64_t *c = (const uint64_t *)(M.absb + (size_t)ai * 2 * K);
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            const uint64_t w = gload<uint64_t>(c + k);
-            out[2 * k] = __uint_as_float((uint32_t)w);
-            out[2 * k + 1] = __uint_as_float((uint32_t)(w >> 32));
-        }
     } else {
         const float scale = 1.0f / (float)(1u << (BITS & 31));
 #pragma unroll
@@ -308,6 +302,41 @@ __device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, c
             out[2 * k + 1] = __builtin_fmaf(-(float)qh, s, Ph);
         }
     }
+}
+
+// an absolute node of a coded model: the first four code bytes hold its
+// index in the FP32 table
+template <int K, int BITS>
+__device__ __forceinline__ void decode_abs(const DevModel &M, const NodeWords<K, BITS> &nw, float out[2 * K])
+{
+    const uint32_t ai = BITS == 8 ? (nw.w[0] | (nw.w[1] << 16)) : nw.w[0];
+    const uint64_t *c = (const uint64_t *)(M.absb + (size_t)ai * 2 * K);
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint64_t w = gload<uint64_t>(c + k);
+        out[2 * k] = __uint_as_float((uint32_t)w);
+        out[2 * k + 1] = __uint_as_float((uint32_t)(w >> 32));
+    }
+}
+
+template <int K, int BITS, typename ParentPtr>
+__device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
+                                             ParentPtr parent, float out[2 * K])
+{
+    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS>(M, nw, out);
+    else decode_rel<K, BITS>(nw, parent, out);
+}
+
+// The traversal's decode of a child whose parent bounds are at hand: the
+// relative decode always runs (so the code words are consumed before any
+// branch and their loads travel together with the topology word's), and
+// the rare treelet tops then read their absolute bounds.
+template <int K, int BITS>
+__device__ __forceinline__ void decode_child(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
+                                             const float *parent, float out[2 * K])
+{
+    decode_rel<K, BITS>(nw, parent, out);
+    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS>(M, nw, out);
 }
 
 template <int K, int BITS, typename ParentPtr>
@@ -381,12 +410,6 @@ __device__ __forceinline__ uint32_t meta_word(uint32_t aoff, uint32_t boff, uint
     return aoff | (boff << 8) | (nb << 16) | (tpre << 24);
 }
 
-struct Counters {
-    unsigned long long bv_tests = 0, tri_tests = 0, tri_fp64 = 0, expansions = 0, node_bytes = 0, tri_bytes = 0,
-                       donated = 0, node_steps = 0, leaf_steps = 0;
-    uint32_t max_entries = 0, max_records = 0, max_steps = 0;
-};
-
 // A donated work item: a node pair that passed its BV test, with both
 // nodes' decoded bounds so that it is self-contained, or a leaf pair.
 //   u32 pose, u32 topo A, u32 topo B, f32 lower bound, f32 A[2K], f32 B[2K]
@@ -412,11 +435,18 @@ __device__ __forceinline__ unsigned long long poll64(unsigned long long *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Wait until this lane's memory operations have completed.  `dep` carries
-// the results of the atomics to wait for, so they are issued in their
-// returning form (complete once performed at the coherence point); the
-// memory clobber keeps the compiler from moving memory operations across.
-__device__ __forceinline__ void wait_mem(uint32_t dep) { asm volatile("s_waitcnt vmcnt(0)" : : "v"(dep) : "memory"); }
+// A device-scope atomic exchange whose old value is not needed: issued in
+// the form that returns nothing, so that many of them travel at once (the
+// returning form would make each wait for its reply before the next).
+__device__ __forceinline__ void rmw_put(uint32_t *p, uint32_t v)
+{
+    (void)__hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every vector memory operation this wave issued has completed
+// (atomics performed at the coherence point included); the memory clobber
+// keeps the compiler from moving memory operations across.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" : : : "memory"); }
+
 
 // node steps between two looks at the queue (for waiting waves to feed;
 // distance queries look less often, below)
@@ -454,45 +484,69 @@ constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 // Collision modes and distance queries of AABB models fit 3 waves per SIMD
 // (168 VGPRs); distance queries of 18-DOP models need more.
 template <int K, int BITS, int MODE>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu((MODE == MODE_DIST && K == 9) ? 2 : 3)))
+__global__ __launch_bounds__(kMaxWavesPerGroup * WAVE)
+__attribute__((amdgpu_waves_per_eu((MODE == MODE_DIST && K == 9) ? 2 : 3)))
 void traverse_kernel(QueryArgs q, StackLimits lim)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t lane = __lane_id();
-    const Layout LY = make_layout(K, MODE, lim);
-    unsigned char *base = lds_raw;
+    const Layout LY = make_layout(K, MODE, lim, (uint32_t)BITS);
+    // a workgroup holds one or more independent waves (the launch's
+    // workgroup shape); each has its own slice of LDS
+    const uint32_t wave_in_group = uni(threadIdx.x / WAVE), waves_per_group = blockDim.x / WAVE;
+    const uint32_t wave_id = blockIdx.x * waves_per_group + wave_in_group;
+    const uint32_t n_waves = gridDim.x * waves_per_group;
+    unsigned char *base = lds_raw + (size_t)wave_in_group * LY.total;
+    constexpr uint32_t RW = rec_words(K);  // floats per record (and per transformed A record)
+    constexpr uint32_t RV = RW / 4;        // float4 per record
+    constexpr bool kTopoEnt = topo_in_entry(MODE);
     float4 *xf = (float4 *)(base + LY.xf);
-    uint32_t *frame_end = (uint32_t *)(base + LY.frame_end);
-    uint32_t *rtopo = (uint32_t *)(base + LY.rtopo);
-    float *rbnd = (float *)(base + LY.rbnd);
+    float *rec = (float *)(base + LY.rec);
     float *ta = (float *)(base + LY.ta);
+    uint32_t *ta_topo = (uint32_t *)(base + LY.ta_topo);
     float4 *tsph = (float4 *)(base + LY.tsph);
-    uint32_t *ent = (uint32_t *)(base + LY.ent);
+    uint32_t *ent = (uint32_t *)(base + LY.ent);      // recA | recB << 13 | frame level << 26
+    uint2 *ent_tp = (uint2 *)(base + LY.ent_tp);      // collision queries: both nodes' topology words
     float *ent_lb = (float *)(base + LY.ent_lb);
     uint2 *lq = (uint2 *)(base + LY.lq);
     float *lq_lb = (float *)(base + LY.lq_lb);
     uint32_t *lscan = (uint32_t *)(base + LY.lscan);  // leaf step: prefix sums of the taken leaf pairs
-    uint32_t *meta = (uint32_t *)(base + LY.meta);
+    auto rec_topo_ref = [&](uint32_t r) -> uint32_t & { return ((uint32_t *)rec)[(size_t)r * RW + 2 * K]; };
 
-    constexpr uint32_t IW = words_of_item(K);
-    constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass       // dwords per item
+    constexpr uint32_t IW = words_of_item(K);       // dwords per item
+    constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass
     constexpr uint32_t IPI = (uint32_t)WAVE / IW;   // items written per wave instruction
     const DevModel &MA = q.A;
     DevModel MB = q.B;  // the fixed model of the current unit (per pose in batched queries)
     WsHeader *hdr = q.ws.hdr;
-    Counters cnt;
+    // this wave's statistics counters (C_* rows), kept in LDS so that they
+    // hold no registers; lane 0 updates them with LDS atomics
+    unsigned long long *ctr = (unsigned long long *)(base + LY.ctr);
+    if (lane < (uint32_t)C_NUM) ctr[lane] = 0;
+    auto ctr_add = [&](int c, unsigned long long v) {
+        __hip_atomic_fetch_add(&ctr[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto ctr_max = [&](int c, unsigned long long v) {
+        __hip_atomic_fetch_max(&ctr[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     uint32_t lq_trigger_full = (uint32_t)(WAVE / (MA.leaf_size * MB.leaf_size));
     const uint32_t code_bytes_A = 4 + MA.stride;
     uint32_t code_bytes_B = 4 + MB.stride;
     const bool can_donate = !q.no_split;
     unsigned long long t_first = 0, t_drain = ~0ull;
 
+    // the two topology words of entry i
+    auto entry_topo = [&](uint32_t i, uint32_t e) -> uint2 {
+        if constexpr (kTopoEnt) return ent_tp[i];
+        else return make_uint2(rec_topo_ref(e & REC_MASK), rec_topo_ref((e >> REC_BITS) & REC_MASK));
+    };
+
     // Publish items: reserve n slots of the item queue, fill them from
     // entries [0, n_ent) and leaf pairs [0, n - n_ent), then mark them
     // ready.  Returns the number of items published (n, or 0 if the queue
     // is full; the slots reserved below its end are then published void).
     auto publish = [&](uint32_t pose, uint32_t n, uint32_t n_ent, float best) -> uint32_t {
-        uint32_t first = 0, ok = 0, sink = 0, left = 0;
+        uint32_t first = 0, ok = 0, left = 0;
         // once helpers have begun to leave, a claimed slot may have nobody
         // behind it: publish nothing (this unit's own count in `pending`
         // keeps any helper from leaving while it publishes)
@@ -502,17 +556,17 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             first = rmw_add(&hdr->q_tail, n);
             ok = first + n <= q.ws.item_cap && first + n >= first;
             if (ok) {
-                sink ^= rmw_add(&hdr->pending, n);
+                (void)rmw_add(&hdr->pending, n);
                 if (MODE == MODE_DIST && best < INFINITY)
-                    sink ^= __hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best), __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    (void)__hip_atomic_fetch_min(&q.ws.best32[pose], __float_as_uint(best), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         ok = uni(ok);
         first = uni(first);
         if (!ok) {
             for (uint32_t i = lane; i < n && first + i < q.ws.item_cap; i += WAVE)
-                sink ^= rmw_xchg(&q.ws.items[(size_t)(first + i) * IW], kVoidItem);
+                rmw_put(&q.ws.items[(size_t)(first + i) * IW], kVoidItem);
         } else {
             for (uint32_t i0 = 0; i0 < n; i0 += IPI) {
                 const uint32_t i = i0 + lane / IW, w = lane % IW;
@@ -523,11 +577,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         const uint32_t ee = ent[i];
                         const uint32_t rA = ee & REC_MASK, rB = (ee >> REC_BITS) & REC_MASK;
                         if (w == 0) val = pose;
-                        else if (w == 1) val = rtopo[rA];
-                        else if (w == 2) val = rtopo[rB];
+                        else if (w == 1) val = entry_topo(i, ee).x;
+                        else if (w == 2) val = entry_topo(i, ee).y;
                         else if (w == 3) val = MODE == MODE_DIST ? __float_as_uint(ent_lb[i]) : 0u;
-                        else if (w < 4 + 2 * K) val = __float_as_uint(rbnd[(size_t)rA * 2 * K + (w - 4)]);
-                        else val = __float_as_uint(rbnd[(size_t)rB * 2 * K + (w - 4 - 2 * K)]);
+                        else if (w < 4 + 2 * K) val = __float_as_uint(rec[(size_t)rA * RW + (w - 4)]);
+                        else val = __float_as_uint(rec[(size_t)rB * RW + (w - 4 - 2 * K)]);
                     } else {
                         const uint32_t j = i - n_ent;
                         const uint2 le = lq[j];
@@ -537,13 +591,56 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         else if (w == 3) val = MODE == MODE_DIST ? __float_as_uint(lq_lb[j]) : 0u;
                         else write = false;  // a leaf pair needs no bounds
                     }
-                    if (write) sink ^= rmw_xchg(&q.ws.items[(size_t)(first + i) * IW + w], val);
+                    if (write) rmw_put(&q.ws.items[(size_t)(first + i) * IW + w], val);
                 }
             }
         }
-        wait_mem(sink);
-        for (uint32_t i = lane; i < n && first + i < q.ws.item_cap; i += WAVE) rmw_xchg(&q.ws.ready[first + i], 1u);
+        // every payload word and the pending count are in place before any
+        // ready flag is set
+        wait_mem();
+        for (uint32_t i = lane; i < n && first + i < q.ws.item_cap; i += WAVE) rmw_put(&q.ws.ready[first + i], 1u);
         return ok ? n : 0u;
+    };
+
+    // An A record of the current frame (index c within it, lane holding its
+    // bounds and topology word) prepared for the child-pair tests: its
+    // topology word beside the transformed records, and for AABB models or
+    // distance queries its circumscribed sphere (centre placed by the pose)
+    // and half extents in its own frame.
+    Pose P;
+    float rot_eps = 0.0f;
+    auto prep_A = [&](uint32_t c, const float *b, uint32_t topo) {
+        ta_topo[c] = topo;
+        if constexpr (MODE == MODE_DIST || K == 3) {
+            V3<float> cc = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
+            float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
+            // the map stretches lengths by at most 1 + 1.5 rot_eps
+            float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f + 2.0f * rot_eps);
+            V3<float> cw = xform_f32(P, cc);
+            tsph[2 * c] = make_float4(cw.x, cw.y, cw.z, r);
+            tsph[2 * c + 1] = make_float4(hx, hy, hz, hx + hy + hz);  // A-frame half extents
+        }
+    };
+    auto store_rec = [&](uint32_t r, const float *b, uint32_t topo) {
+        float t[RW];
+#pragma unroll
+        for (uint32_t k = 0; k < 2 * K; k++) t[k] = b[k];
+        t[2 * K] = __uint_as_float(topo);
+        t[2 * K + 1] = 0.0f;
+        float4 *dst = (float4 *)(rec + (size_t)r * RW);
+#pragma unroll
+        for (uint32_t v = 0; v < RV; v++) dst[v] = make_float4(t[4 * v], t[4 * v + 1], t[4 * v + 2], t[4 * v + 3]);
+    };
+    auto load_rec = [&](uint32_t r, float *b) {
+        const float4 *src = (const float4 *)(rec + (size_t)r * RW);
+#pragma unroll
+        for (uint32_t v = 0; v < RV; v++) {
+            const float4 x = src[v];
+            b[4 * v] = x.x;
+            b[4 * v + 1] = x.y;
+            b[4 * v + 2] = x.z;
+            b[4 * v + 3] = x.w;
+        }
     };
 
     bool poses_left = true, first_claim = true;
@@ -554,13 +651,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     // waits complete it long before it could publish.)  A wave whose block
     // index is past the poses gets none from the queue either: it holds no
     // count and goes straight to helping or exits.
-    const bool counted = can_donate && blockIdx.x < q.n_poses;
+    const bool counted = can_donate && wave_id < q.n_poses;
     if (counted && lane == 0) rmw_add(&hdr->pending, 1u);
     uint32_t cur_pose = 0xFFFFFFFFu;
-    Pose P;
-    float e_abs = 0.0f, e_sph = 0.0f, e_dir = 0.0f, rot_eps = 0.0f;
-    // this lane's slab (lane mod K) of the pose's support-function transform
+    float e_abs = 0.0f, e_sph = 0.0f, e_dir = 0.0f;
+    // this lane's slab (lane mod K) of the pose's support-function transform,
+    // kept in registers for the whole pose
     const uint32_t my_k = lane % (uint32_t)K;
+    float4 xf0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float xfU = 0.0f, xfL = 0.0f;
     const float w_diag = 0.70710676f;  // <= 1/sqrt(2): unit-length correction of diagonal slabs
 
     for (;;) {
@@ -572,8 +671,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         if (poses_left) {
             // a wave's first pose is its block index; later ones come from
             // the queue (no burst of atomics on one line at the start)
-            uint32_t p = blockIdx.x;
-            if (!first_claim && lane == 0) p = gridDim.x + atomicAdd(&hdr->pose_next, 1u);
+            uint32_t p = wave_id;
+            if (!first_claim && lane == 0) p = n_waves + atomicAdd(&hdr->pose_next, 1u);
             first_claim = false;
             // (queue claims start at the grid size, past any block index)
             pose = uni(p);
@@ -588,9 +687,10 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         }
         if (!poses_left) {
             if (!can_donate) break;
-            // the waves with the lowest block indices (spread over the XCDs
-            // and CUs by the dispatcher) stay as helpers; the others exit
-            if (blockIdx.x >= q.max_helpers) break;
+            // the first waves of the workgroups with the lowest indices
+            // (spread over the XCDs and CUs by the dispatcher) stay as
+            // helpers; the others exit
+            if (blockIdx.x >= q.max_helpers || wave_in_group != 0) break;
             uint32_t slot = 0;
             if (lane == 0) slot = rmw_add(&hdr->q_head, 1u);
             slot = uni(slot);
@@ -638,7 +738,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             it_tA = lane_of(v, 1);
             it_tB = lane_of(v, 2);
             it_lb = __uint_as_float(lane_of(v, 3));
-            if (lane >= 4 && lane < IW) rbnd[lane - 4] = __uint_as_float(v);
+            // records 0 and 1 hold the item's two decoded BVs
+            if (lane >= 4 && lane < 4 + 2 * K) rec[lane - 4] = __uint_as_float(v);
+            if (lane >= 4 + 2 * K && lane < IW) rec[RW + (lane - 4 - 2 * K)] = __uint_as_float(v);
             from_item = true;
             if (MODE == MODE_BOOL) {
                 uint32_t decided = 0;
@@ -694,12 +796,21 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             // rounding allowance of the directional gap below: the sphere
             // bound's, grown with the matrix's largest stretch
             e_dir = __builtin_fmaf(2.0f * rot_eps, e_sph, e_sph);
+            wave_sync();
+            // this lane's slab of the support-function transform
+            const float4 x0 = xf[2 * my_k], x1 = xf[2 * my_k + 1];
+            xf0 = x0;
+            xfU = x1.x;
+            xfL = x1.y;
         }
 
         // ---- initial state ----
         // current frame: the records decoded by the last node step, waiting
-        // for their child-pair tests (f_ns entries described in `meta`)
-        uint32_t f_id = 0, f_base = 0, f_nA = 1, f_ns = 1, f_tasks = 1;
+        // for their child-pair tests (f_ns entries, described in f_meta)
+        uint32_t f_base = 0, f_nA = 1, f_ns = 1, f_tasks = 1, f_level = 0;
+        uint32_t f_meta = meta_word(0, 1, 1, 0);  // lane s: entry s of the frame
+        // lane l: end of the frame of level l (frames are stacked in record space)
+        uint32_t fe_v = lane == 0 ? 2u : 0u;
         bool have_frame;
         uint32_t top = 0, lq_count = 0;
         bool hit = false, overflow = false, pair_overflow = false, fix_overflow = false;
@@ -718,17 +829,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 load_node<K, BITS>(M, 0, tw, nw);
                 float bnd[2 * K];
                 decode_words<K, BITS>(M, tw, nw, (const float *)nullptr, bnd);
-                rtopo[lane] = tw;
-#pragma unroll
-                for (int k = 0; k < 2 * K; k++) rbnd[2 * K * lane + k] = bnd[k];
+                store_rec(lane, bnd, tw);
+                if (lane == 0) prep_A(0, bnd, tw);
             }
-            if (lane == 0) meta[0] = meta_word(0, 1, 1, 0);
             have_frame = true;
         } else {
             // the item's pair already passed its BV test: records 0 and 1 hold it
             if (lane == 0) {
-                rtopo[0] = it_tA;
-                rtopo[1] = it_tB;
+                rec_topo_ref(0) = it_tA;
+                rec_topo_ref(1) = it_tB;
             }
             if (topo_leaf(it_tA) && topo_leaf(it_tB)) {
                 if (lane == 0) {
@@ -739,6 +848,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             } else {
                 if (lane == 0) {
                     ent[0] = 0u | (1u << REC_BITS);
+                    if constexpr (kTopoEnt) ent_tp[0] = make_uint2(it_tA, it_tB);
                     if (MODE == MODE_DIST) ent_lb[0] = it_lb;
                 }
                 top = 1;
@@ -750,7 +860,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             }
             have_frame = false;
         }
-        if (lane == 0) frame_end[0] = 2;
         wave_sync();
 
         uint32_t steps = 0;
@@ -767,186 +876,179 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             if (have_frame) {
                 have_frame = false;
                 // -------- transform A's records of the frame into B's frame --------
-                // lane = (record c, slab my_k), CPL records per pass, two passes
-                // at a time; each generator reads its slab's (lo, hi) pair at once
-                // (distance tests of AABB models read only the spheres below)
+                // lane = (record c, slab my_k), CPL records per pass; each
+                // generator reads its slab's (lo, hi) pair at once (distance
+                // tests of AABB models read only the spheres prepared at decode)
                 if constexpr (MODE != MODE_DIST || K != 3) {
-                    const float4 x0 = xf[2 * my_k], x1 = xf[2 * my_k + 1];
-                    const uint32_t up = __float_as_uint(x0.w);
+                    const uint32_t up = __float_as_uint(xf0.w);
                     const uint32_t a0 = (up & 0xFFu) >> 1, a1 = ((up >> 8) & 0xFFu) >> 1, a2 = ((up >> 16) & 0xFFu) >> 1;
                     const bool h0 = (up & 1u) != 0, h1 = (up & 0x100u) != 0, h2 = (up & 0x10000u) != 0;
-                    auto move = [&](uint32_t c, float2 p0, float2 p1, float2 p2) {
-                        // U takes each generator's hi for + signs (lo for -), L the other bound
-                        const float U = __builtin_fmaf(x0.z, h2 ? p2.y : p2.x,
-                                                       __builtin_fmaf(x0.y, h1 ? p1.y : p1.x, __builtin_fmaf(x0.x, h0 ? p0.y : p0.x, x1.x)));
-                        const float L = __builtin_fmaf(x0.z, h2 ? p2.x : p2.y,
-                                                       __builtin_fmaf(x0.y, h1 ? p1.x : p1.y, __builtin_fmaf(x0.x, h0 ? p0.x : p0.y, x1.y)));
-                        *(float2 *)(ta + 2 * K * c + 2 * my_k) = make_float2(L, U);
-                    };
+                    const uint32_t my_c = lane / (uint32_t)K;
                     for (uint32_t c0 = 0; c0 < f_nA; c0 += CPL) {
-                        const uint32_t ca = c0 + lane / (uint32_t)K;
+                        const uint32_t ca = c0 + my_c;
                         if (lane < CPL * (uint32_t)K && ca < f_nA) {
-                            const float2 *b = (const float2 *)(rbnd + (size_t)(f_base + ca) * 2 * K);
-                            move(ca, b[a0], b[a1], b[a2]);
+                            const float2 *b = (const float2 *)(rec + (size_t)(f_base + ca) * RW);
+                            const float2 p0 = b[a0], p1 = b[a1], p2 = b[a2];
+                            // U takes each generator's hi for + signs (lo for -), L the other bound
+                            const float U = __builtin_fmaf(xf0.z, h2 ? p2.y : p2.x,
+                                                           __builtin_fmaf(xf0.y, h1 ? p1.y : p1.x, __builtin_fmaf(xf0.x, h0 ? p0.y : p0.x, xfU)));
+                            const float L = __builtin_fmaf(xf0.z, h2 ? p2.x : p2.y,
+                                                           __builtin_fmaf(xf0.y, h1 ? p1.x : p1.y, __builtin_fmaf(xf0.x, h0 ? p0.x : p0.y, xfL)));
+                            *(float2 *)(ta + (size_t)ca * RW + 2 * my_k) = make_float2(L, U);
                         }
                     }
+                    wave_sync();
                 }
-                if ((MODE == MODE_DIST || K == 3) && lane < f_nA) {
-                    // circumscribed sphere of the record's box, centre moved by the pose
-                    const float *b = rbnd + (size_t)(f_base + lane) * 2 * K;
-                    V3<float> c = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
-                    float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
-                    // the map stretches lengths by at most 1 + 1.5 rot_eps
-                    float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f + 2.0f * rot_eps);
-                    V3<float> cw = xform_f32(P, c);
-                    tsph[2 * lane] = make_float4(cw.x, cw.y, cw.z, r);
-                    tsph[2 * lane + 1] = make_float4(hx, hy, hz, hx + hy + hz);  // A-frame half extents
-                }
-                wave_sync();
-                // -------- child-pair tests, 64 per pass --------
-                uint32_t mw[PMAX];
-#pragma unroll
-                for (int s = 0; s < PMAX; s++) mw[s] = meta[s];
+                // -------- child-pair tests, one per lane --------
                 const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
-                const uint32_t top0 = top;
-                float near_lb = INFINITY;
-                uint32_t near_slot = 0;
-                for (uint32_t t0 = 0; t0 < f_tasks; t0 += WAVE) {
-                    const uint32_t t = t0 + lane;
-                    bool survive = false;
-                    float lb = 0.0f;
-                    uint32_t recA = 0, recB = 0, tA_w = 0, tB_w = 0;
-                    if (t < f_tasks) {
-                        // the task's entry: the last one whose first task is <= t
-                        uint32_t w = mw[0];
+                bool survive = false;
+                float lb = 0.0f;
+                uint32_t recA = 0, recB = 0, tA_w = 0, tB_w = 0;
+                if (lane < f_tasks) {
+                    // the task's entry: the last one whose first task is <= lane
+                    // (culled entries of distance queries have no tasks and are
+                    // passed over)
+                    uint32_t w = lane_of(f_meta, 0);
 #pragma unroll
-                        for (int s = 1; s < PMAX; s++)
-                            if ((uint32_t)s < f_ns && (mw[s] >> 24) <= t) w = mw[s];
-                        const uint32_t aoff = w & 0xFFu, boff = (w >> 8) & 0xFFu, nb = (w >> 16) & 0xFFu;
-                        const uint32_t local = t - (w >> 24);
-                        const uint32_t i = (local * recip16(nb)) >> 16, j = local - i * nb;
-                        const uint32_t ia = aoff + i;
-                        recA = f_base + ia;
-                        recB = f_base + boff + j;
-                        // topology words load with the bounds (one LDS round trip)
-                        tA_w = rtopo[recA];
-                        tB_w = rtopo[recB];
-                        const float *tA = ta + 2 * K * ia;
-                        const float *bB = rbnd + (size_t)recB * 2 * K;
-                        if (MODE == MODE_DIST) {
-                            // A lower bound on the distance of the two BVs (the largest of
-                            // the ones below); where the boxes overlap it is negative, and
-                            // then its value orders the traversal: the most deeply
-                            // overlapping pair goes first, which reaches close triangle
-                            // pairs (or an intersection, distance 0, which ends the pose)
-                            // sooner than taking overlapping pairs in lane order.
-                            // First: gaps of the 18-DOP slabs (AABB models skip them: beside
-                            // the directional gap below they pruned no more and cost time)
-                            float g = -INFINITY;
-                            if constexpr (K != 3) {
+                    for (int s = 1; s < PMAX; s++) {
+                        if ((uint32_t)s < f_ns) {
+                            const uint32_t ws = lane_of(f_meta, s);
+                            if ((ws >> 24) <= lane) w = ws;
+                        }
+                    }
+                    const uint32_t aoff = w & 0xFFu, boff = (w >> 8) & 0xFFu, nb = (w >> 16) & 0xFFu;
+                    const uint32_t local = lane - (w >> 24);
+                    // local / nb (local < 64, nb <= 8): the half offset keeps the
+                    // product away from integers, so one rounding cannot move it
+                    const uint32_t i = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)nb));
+                    const uint32_t j = local - i * nb;
+                    const uint32_t ia = aoff + i;
+                    recA = f_base + ia;
+                    recB = f_base + boff + j;
+                    tA_w = ta_topo[ia];
+                    float bB[RW];
+                    load_rec(recB, bB);
+                    tB_w = __float_as_uint(bB[2 * K]);
+                    if constexpr (MODE == MODE_DIST) {
+                        // A lower bound on the distance of the two BVs (the largest of
+                        // the ones below); where the boxes overlap it is negative, and
+                        // then its value orders the traversal: the most deeply
+                        // overlapping pair goes first, which reaches close triangle
+                        // pairs (or an intersection, distance 0, which ends the pose)
+                        // sooner than taking overlapping pairs in lane order.
+                        // First: gaps of the 18-DOP slabs (AABB models skip them: beside
+                        // the directional gap below they pruned no more and cost time)
+                        float g = -INFINITY;
+                        if constexpr (K != 3) {
+                            float tA[RW];
+                            {
+                                const float4 *src = (const float4 *)(ta + (size_t)ia * RW);
 #pragma unroll
-                                for (int k = 0; k < K; k++) {
-                                    float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
-                                    gk *= (k < 3 ? 1.0f : w_diag);
-                                    g = fmaxf(g, gk);
+                                for (uint32_t v = 0; v < RV; v++) {
+                                    const float4 x = src[v];
+                                    tA[4 * v] = x.x, tA[4 * v + 1] = x.y, tA[4 * v + 2] = x.z, tA[4 * v + 3] = x.w;
                                 }
                             }
-                            // second lower bound: distance of the circumscribed spheres
-                            float4 sa = tsph[2 * ia];
-                            float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
-                            float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
-                            float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
-                            float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
-                            float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
-                            // third lower bound: the gap along one well-chosen direction
-                            // (gaps along A's own axes, tried beside it, pruned no more)
-                            const float gd = dir_gap(P.R, sa, tsph[2 * ia + 1], bB, dx, dy, dz, hx, hy, hz, e_dir);
-                            lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), gd);  // g is -inf for AABB models
-                            survive = lb <= tau;
-                        } else {
-                            bool sep = false;
-                            float ov = INFINITY;
 #pragma unroll
                             for (int k = 0; k < K; k++) {
-                                sep |= (tA[2 * k] > bB[2 * k + 1]) | (tA[2 * k + 1] < bB[2 * k]);
-                                if (MODE == MODE_BOOL)
-                                    ov = fminf(ov, fminf(tA[2 * k + 1], bB[2 * k + 1]) - fmaxf(tA[2 * k], bB[2 * k]));
+                                float gk = fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]);
+                                gk *= (k < 3 ? 1.0f : w_diag);
+                                g = fmaxf(g, gk);
                             }
-                            if constexpr (K == 3) {
-                                // separating axes along A's own axes (the rotation's
-                                // columns): A's record as a box in its frame, B's as an
-                                // axis-aligned box; separated only beyond the allowances
-                                // for non-orthonormal columns and FP32 rounding (AABB
-                                // models only: an 18-DOP's diagonal slabs already cut
-                                // what these axes would, and the test costs more than
-                                // it saves there)
-                                const float4 sa = tsph[2 * ia], ea = tsph[2 * ia + 1];
-                                const float dx = 0.5f * (bB[0] + bB[1]) - sa.x, dy = 0.5f * (bB[2] + bB[3]) - sa.y,
-                                            dz = 0.5f * (bB[4] + bB[5]) - sa.z;
-                                const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]),
-                                            hz = 0.5f * (bB[5] - bB[4]);
-                                float ga = -INFINITY;
+                        }
+                        // second lower bound: distance of the circumscribed spheres
+                        const float4 sa = tsph[2 * ia];
+                        const float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
+                        const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
+                        const float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                        const float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
+                        const float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
+                        // third lower bound: the gap along one well-chosen direction
+                        // (gaps along A's own axes, tried beside it, pruned no more)
+                        const float gd = dir_gap(P.R, sa, tsph[2 * ia + 1], bB, dx, dy, dz, hx, hy, hz, e_dir);
+                        lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), gd);  // g is -inf for AABB models
+                        survive = lb <= tau;
+                    } else {
+                        // the largest gap between A's moved slab interval and B's:
+                        // positive separates; otherwise its value (minus the
+                        // translation that separates the pair along its best
+                        // slab) orders the traversal, the deepest overlap first
+                        float tA[RW];
+                        {
+                            const float4 *src = (const float4 *)(ta + (size_t)ia * RW);
 #pragma unroll
-                                for (int i = 0; i < 3; i++) {
-                                    const float c0 = P.R[i], c1 = P.R[3 + i], c2 = P.R[6 + i];
-                                    const float p = __builtin_fmaf(c0, dx, __builtin_fmaf(c1, dy, c2 * dz));
-                                    const float rbi =
-                                        __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
-                                    ga = fmaxf(ga, fabsf(p) - (i == 0 ? ea.x : i == 1 ? ea.y : ea.z) - rbi);
-                                }
-                                ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
-                                sep |= ga > 0.0f;
+                            for (uint32_t v = 0; v < RV; v++) {
+                                const float4 x = src[v];
+                                tA[4 * v] = x.x, tA[4 * v + 1] = x.y, tA[4 * v + 2] = x.z, tA[4 * v + 3] = x.w;
                             }
-                            survive = !sep;
-                            // early exit: the most deeply overlapping pair is expanded first
-                            lb = -ov;
                         }
-                    }
-                    // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
-                    const bool ll = topo_leaf(tA_w) && topo_leaf(tB_w);
-                    const uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(survive && !ll);
-                    const uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
-                    if (survive && ll) {
-                        const uint32_t slot = lq_count + mbcnt(m_ll);
-                        lq[slot] = make_uint2(tA_w, tB_w);
-                        if (MODE == MODE_DIST) lq_lb[slot] = lb;
-                    }
-                    if (survive && !ll) {
-                        const uint32_t slot = top + mbcnt(m_nd);
-                        ent[slot] = recA | (recB << REC_BITS) | (f_id << (2 * REC_BITS));
-                        if (MODE == MODE_DIST) ent_lb[slot] = lb;
-                    }
-                    if ((MODE == MODE_DIST || MODE == MODE_BOOL) && n_nd > 0) {
-                        // remember the most promising new node pair: the closest
-                        // (distance) or the most deeply overlapping (collision)
-                        const float mlb = wave_min((survive && !ll) ? lb : INFINITY);
-                        if (mlb < near_lb) {
-                            const uint64_t win = __ballot(survive && !ll && lb == mlb);
-                            const uint32_t wl = (uint32_t)__ffsll((unsigned long long)win) - 1u;
-                            near_lb = mlb;
-                            near_slot = top + (uint32_t)__popcll(m_nd & ((1ull << wl) - 1ull));
+                        float g = -INFINITY;
+#pragma unroll
+                        for (int k = 0; k < K; k++)
+                            g = fmaxf(g, fmaxf(tA[2 * k] - bB[2 * k + 1], bB[2 * k] - tA[2 * k + 1]));
+                        bool sep = g > 0.0f;
+                        if constexpr (K == 3) {
+                            // separating axes along A's own axes (the rotation's
+                            // columns): A's record as a box in its frame, B's as an
+                            // axis-aligned box; separated only beyond the allowances
+                            // for non-orthonormal columns and FP32 rounding (AABB
+                            // models only: an 18-DOP's diagonal slabs already cut
+                            // what these axes would, and the test costs more than
+                            // it saves there)
+                            const float4 sa = tsph[2 * ia], ea = tsph[2 * ia + 1];
+                            const float dx = 0.5f * (bB[0] + bB[1]) - sa.x, dy = 0.5f * (bB[2] + bB[3]) - sa.y,
+                                        dz = 0.5f * (bB[4] + bB[5]) - sa.z;
+                            const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]),
+                                        hz = 0.5f * (bB[5] - bB[4]);
+                            float ga = -INFINITY;
+#pragma unroll
+                            for (int a = 0; a < 3; a++) {
+                                const float c0 = P.R[a], c1 = P.R[3 + a], c2 = P.R[6 + a];
+                                const float p = __builtin_fmaf(c0, dx, __builtin_fmaf(c1, dy, c2 * dz));
+                                const float rbi =
+                                    __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
+                                ga = fmaxf(ga, fabsf(p) - (a == 0 ? ea.x : a == 1 ? ea.y : ea.z) - rbi);
+                            }
+                            ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
+                            sep |= ga > 0.0f;
                         }
-                    }
-                    lq_count += n_ll;
-                    top += n_nd;
-                }
-                if ((MODE == MODE_DIST || MODE == MODE_BOOL) && top - top0 > 1 && near_slot != top - 1) {
-                    // put the most promising new pair on top of the stack
-                    wave_sync();
-                    if (lane == 0) {
-                        const uint32_t last = top - 1;
-                        const uint32_t e0 = ent[near_slot];
-                        ent[near_slot] = ent[last];
-                        ent[last] = e0;
-                        if (MODE == MODE_DIST) {
-                            const float l0 = ent_lb[near_slot];
-                            ent_lb[near_slot] = ent_lb[last];
-                            ent_lb[last] = l0;
-                        }
+                        survive = !sep;
+                        lb = g;
                     }
                 }
-                cnt.bv_tests += f_tasks;
-                cnt.max_entries = max(cnt.max_entries, top);
+                // -------- compaction: leaf pairs -> leaf queue, others -> entries --------
+                const bool ll = topo_leaf(tA_w) && topo_leaf(tB_w);
+                const bool nd = survive && !ll;
+                const uint64_t m_ll = __ballot(survive && ll), m_nd = __ballot(nd);
+                const uint32_t n_ll = __popcll(m_ll), n_nd = __popcll(m_nd);
+                if (survive && ll) {
+                    const uint32_t slot = lq_count + mbcnt(m_ll);
+                    lq[slot] = make_uint2(tA_w, tB_w);
+                    if (MODE == MODE_DIST) lq_lb[slot] = lb;
+                }
+                // the most promising new node pair, the closest (distance) or
+                // the most deeply overlapping (collision), goes on top of the
+                // stack: it is expanded next
+                uint64_t win = 0;
+                if ((MODE == MODE_DIST || MODE == MODE_BOOL) && n_nd > 1) {
+                    const float mlb = wave_min(nd ? lb : INFINITY);
+                    const uint64_t cand = __ballot(nd && lb == mlb);
+                    win = cand & (~cand + 1ull);
+                }
+                const uint32_t my_packed = recA | (recB << REC_BITS) | (f_level << (2 * REC_BITS));
+                if (nd) {
+                    const uint32_t slot =
+                        ((win >> lane) & 1ull) ? top + n_nd - 1u : top + mbcnt(m_nd & ~win);
+                    ent[slot] = my_packed;
+                    if constexpr (kTopoEnt) ent_tp[slot] = make_uint2(tA_w, tB_w);
+                    if (MODE == MODE_DIST) ent_lb[slot] = lb;
+                }
+                lq_count += n_ll;
+                top += n_nd;
+                if (lane == 0) {
+                    ctr_add(C_BV_TESTS, f_tasks);
+                    ctr_max(C_MAX_ENTRIES, top);
+                }
                 wave_sync();
             }
             if (MODE == MODE_BOOL && hit) break;
@@ -1044,7 +1146,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         if (keep) tq[n_full + mbcnt(mk)] = make_uint2(tA, tB);
                         n_full += __popcll(mk);
                     }
-                    cnt.tri_bytes += 72ull * total;
+                    if (lane == 0) ctr_add(C_TRI_BYTES, 72ull * total);
                     wave_sync();
                 }
                 for (uint32_t p0 = 0; p0 < n_full; p0 += WAVE) {
@@ -1077,9 +1179,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                             dres = res != 1 ? tri_dist_f32(a, b) : 0.0f;
                         }
                     }
-                    cnt.tri_tests += n_pass;
-                    cnt.leaf_steps++;
-                    if (!screen) cnt.tri_bytes += 72ull * n_pass;
+                    if (lane == 0) {
+                        ctr_add(C_TRI_TESTS, n_pass);
+                        ctr_add(C_LEAF_STEPS, 1);
+                        if (!screen) ctr_add(C_TRI_BYTES, 72ull * n_pass);
+                    }
                     // leaf pairs for the FP64 stage: undecided intersections, and
                     // distances that could be the minimum
                     bool defer;
@@ -1135,7 +1239,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                             if (idx < q.ws.fix_cap) q.ws.fix[idx] = make_uint4(pose, triA, triB, dw);
                         }
                         if (f0 + nd > q.ws.fix_cap) fix_overflow = true;
-                        cnt.tri_fp64 += nd;
+                        if (lane == 0) ctr_add(C_TRI_FP64, nd);
                     }
                     if constexpr (!kScreens) break;  // one pass: at most 64 pairs were taken
                 }
@@ -1155,25 +1259,29 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     unsigned long long ht = poll64((unsigned long long *)&hdr->q_head);
                     uint32_t h = (uint32_t)ht, t = (uint32_t)(ht >> 32);
                     const uint32_t share = q.donate_keep ? (top > q.donate_keep ? top - q.donate_keep : 0u) : top / 2;
+                    // waiting helpers (claimed slots not yet filled) take what they claimed
                     want = h > t ? min(h - t, min(share, q.max_donate)) : 0u;
                 }
                 want = uni(want);
                 if (want && publish(pose, want, want, best32) == want) {
-                    cnt.donated += want;
+                    if (lane == 0) ctr_add(C_DONATED, want);
                     shared = true;
                     // the remaining entries move down (their records stay put)
                     const uint32_t rem = top - want;
                     for (uint32_t b0 = 0; b0 < rem; b0 += WAVE) {
                         const uint32_t i = b0 + lane;
                         uint32_t ev = 0;
+                        uint2 tv = make_uint2(0, 0);
                         float lv = 0.0f;
                         if (i < rem) {
                             ev = ent[want + i];
+                            if constexpr (kTopoEnt) tv = ent_tp[want + i];
                             if (MODE == MODE_DIST) lv = ent_lb[want + i];
                         }
                         wave_sync();
                         if (i < rem) {
                             ent[i] = ev;
+                            if constexpr (kTopoEnt) ent_tp[i] = tv;
                             if (MODE == MODE_DIST) ent_lb[i] = lv;
                         }
                         wave_sync();
@@ -1182,19 +1290,21 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 }
             }
 
+
             // -------- node step: pop the top entries whose children fit one decode pass --------
             const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
-            // lane l <= PMAX reads the (l+1)-th entry from the top
-            uint32_t my_e = 0, my_pA = 0, my_pB = 0, my_fend = 0, my_na = 0, my_nb = 0;
+            // lane l <= PMAX reads the (l+1)-th entry from the top, with both
+            // topology words (collision queries keep them in the entry)
+            uint32_t my_e = 0, my_tA = 0, my_tB = 0, my_na = 0, my_nb = 0;
             if (lane <= (uint32_t)PMAX && lane < top) {
-                my_e = ent[top - 1 - lane];
-                const uint32_t rA = my_e & REC_MASK, rB = (my_e >> REC_BITS) & REC_MASK;
-                my_pA = rtopo[rA];
-                my_pB = rtopo[rB];
-                my_fend = frame_end[my_e >> (2 * REC_BITS)];
-                my_na = topo_leaf(my_pA) ? 1u : topo_count(my_pA);
-                my_nb = topo_leaf(my_pB) ? 1u : topo_count(my_pB);
-                if (MODE == MODE_DIST && ent_lb[top - 1 - lane] > tau) my_na = my_nb = 0;  // culled
+                const uint32_t idx = top - 1 - lane;
+                my_e = ent[idx];
+                const uint2 tp = entry_topo(idx, my_e);
+                my_tA = tp.x;
+                my_tB = tp.y;
+                my_na = topo_leaf(my_tA) ? 1u : topo_count(my_tA);
+                my_nb = topo_leaf(my_tB) ? 1u : topo_count(my_tB);
+                if (MODE == MODE_DIST && ent_lb[idx] > tau) my_na = my_nb = 0;  // culled
             }
             // inclusive prefix over lanes 0..PMAX-1 of (A records, B records, tests,
             // expanded entries), packed in one word (8, 8, 10 and 6 bits)
@@ -1208,11 +1318,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             pk += row_shr<4>(pk);
             const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = (pk >> 16) & 0x3FFu, inX = pk >> 26;
             // with lane+1 entries popped the new frame sits on top of the frame of
-            // the next remaining entry, which lane+1 has read
-            const uint32_t nx_e = row_shl<1>(my_e), nx_fend = row_shl<1>(my_fend);
+            // the next remaining entry (lane+1 read it): its level is one more.
+            // Frames are stacked in record space in level order, so the newest
+            // live frame (the top entry's) ends last: its end bounds where any
+            // new frame can start.
+            const uint32_t nx_e = row_shl<1>(my_e);
             const uint32_t rem_l = top - 1u - lane;
-            const uint32_t nbase_l = rem_l > 0 ? nx_fend : 0u;
             const uint32_t nid_l = rem_l > 0 ? (nx_e >> (2 * REC_BITS)) + 1u : 0u;
+            const uint32_t f_top_end = lane_of(fe_v, (int)(uni(my_e) >> (2 * REC_BITS)));
+            const uint32_t nbase_l = rem_l > 0 ? f_top_end : 0u;
             // proximity queries dive one expansion at a time until a first leaf
             // distance exists: without a bound nothing is culled
             const bool dive = MODE == MODE_DIST && best32 == INFINITY;
@@ -1238,7 +1352,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 // pairs) to the item queue; the unit ends here
                 const uint32_t n_items = top + lq_count;
                 if (can_donate && publish(pose, n_items, top, best32) == n_items) {
-                    cnt.donated += n_items;
+                    if (lane == 0) ctr_add(C_DONATED, n_items);
                     shared = true;
                 } else {
                     overflow = true;
@@ -1249,83 +1363,95 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             const uint32_t nA_tot = lane_of(inA, last), total_rec = nA_tot + lane_of(inB, last);
             const uint32_t tasks_tot = lane_of(inT, last);
             static_assert(TMAX < 1024u && PMAX < 64, "packed prefix fields");
-            const uint32_t new_base = lane_of(nbase_l, last), new_id = lane_of(nid_l, last);
+            const uint32_t new_id = lane_of(nid_l, last);
             top -= n_pop;
-            // popped entries with tests to run get a meta word each; culled ones drop out
-            const bool act = lane < n_pop && my_tk > 0;
-            const uint64_t m_act = __ballot(act);
-            const uint32_t ns = __popcll(m_act);
+            // the new frame starts where the frame of the next remaining entry ends
+            const uint32_t new_base = top > 0 ? lane_of(fe_v, (int)new_id - 1) : 0u;
+            const uint32_t ns = __popcll(__ballot(lane < n_pop && my_tk > 0));
             if (ns == 0) continue;
-            if (act) {
-                const uint32_t ex = pk - my_pk;  // exclusive prefix
-                const uint32_t slot = mbcnt(m_act);
-                meta[slot] = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
-            }
-            // decode: one lane per new record, A records first, then B records
-            // (register staging: the new frame may overwrite the popped
-            // entries' own records).  A record's entry is the popped lane whose
-            // run of records holds it, found from the prefix words read as
-            // scalars; its parent data comes across lanes.
+            // the new frame's entries (culled ones stay, with no tasks): first
+            // A record and first B record in the frame, B's child count, first task
+            const uint32_t ex = pk - my_pk;  // exclusive prefix
+            const uint32_t new_meta = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
+            // decode: one lane per new record, A records first, then B records.
+            // A record's entry is the popped lane whose run of records holds
+            // it (with one popped entry, lane 0's, uniform); its parent data
+            // comes across lanes.
             const bool sideA = lane < nA_tot;
             const uint32_t r = sideA ? lane : lane - nA_tot;
-            uint32_t e = 0, off = 0;
+            uint32_t g_e, g_pA, g_pB, off = 0;
+            if (n_pop == 1) {
+                g_e = uni(my_e);
+                g_pA = uni(my_tA);
+                g_pB = uni(my_tB);
+            } else {
+                uint32_t e = 0;
 #pragma unroll
-            for (int s = 0; s < PMAX; s++) {
-                const uint32_t w = lane_of(pk, s);
-                const uint32_t end = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
-                if ((uint32_t)s < n_pop && end <= r) {
-                    e = (uint32_t)s + 1u;
-                    off = end;
+                for (int s = 0; s < PMAX; s++) {
+                    const uint32_t w = lane_of(pk, s);
+                    const uint32_t end = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
+                    if ((uint32_t)s < n_pop && end <= r) {
+                        e = (uint32_t)s + 1u;
+                        off = end;
+                    }
                 }
+                e = min(e, (uint32_t)PMAX - 1u);
+                g_e = gather(my_e, e);
+                g_pA = gather(my_tA, e);
+                g_pB = gather(my_tB, e);
             }
-            e = min(e, (uint32_t)PMAX - 1u);
-            const uint32_t g_pA = gather(my_pA, e), g_pB = gather(my_pB, e), g_e = gather(my_e, e);
             uint32_t my_topo = 0;
             float my_b[2 * K];
             const bool dec = lane < total_rec;
             {
                 // algorithmic bytes: topology word and codes of every decoded child
                 const bool from_node = dec && !topo_leaf(sideA ? g_pA : g_pB);
-                cnt.node_bytes += (unsigned long long)__popcll(__ballot(from_node && sideA)) * code_bytes_A +
-                                  (unsigned long long)__popcll(__ballot(from_node && !sideA)) * code_bytes_B;
+                const unsigned long long nbytes =
+                    (unsigned long long)__popcll(__ballot(from_node && sideA)) * code_bytes_A +
+                    (unsigned long long)__popcll(__ballot(from_node && !sideA)) * code_bytes_B;
+                if (lane == 0) ctr_add(C_NODE_BYTES, nbytes);
             }
             if (dec) {
                 const uint32_t c = r - off;
                 const uint32_t prec = sideA ? (g_e & REC_MASK) : ((g_e >> REC_BITS) & REC_MASK);
                 const uint32_t ptopo = sideA ? g_pA : g_pB;
-                const float *pb = rbnd + (size_t)prec * 2 * K;
+                float pb[RW];
                 if (topo_leaf(ptopo)) {
+                    // a leaf against an inner node: the leaf itself joins the frame
+                    load_rec(prec, pb);
                     my_topo = ptopo;
 #pragma unroll
                     for (int k = 0; k < 2 * K; k++) my_b[k] = pb[k];
                 } else {
                     const DevModel &M = sideA ? MA : MB;
-                    const uint32_t node = topo_first(ptopo) + c;
                     NodeWords<K, BITS> nw;
-                    load_node<K, BITS>(M, node, my_topo, nw);
-                    decode_words<K, BITS>(M, my_topo, nw, pb, my_b);
+                    load_node<K, BITS>(M, topo_first(ptopo) + c, my_topo, nw);
+                    load_rec(prec, pb);
+                    decode_child<K, BITS>(M, my_topo, nw, pb, my_b);
                 }
             }
             wave_sync();
             if (dec) {
-                rtopo[new_base + lane] = my_topo;
-#pragma unroll
-                for (int k = 0; k < 2 * K; k++) rbnd[(size_t)(new_base + lane) * 2 * K + k] = my_b[k];
+                store_rec(new_base + lane, my_b, my_topo);
+                if (sideA) prep_A(lane, my_b, my_topo);
             }
-            if (lane == 0) frame_end[new_id] = new_base + total_rec;
-            cnt.expansions += ns;
-            cnt.node_steps++;
-            cnt.max_records = max(cnt.max_records, new_base + total_rec);
+            if (lane == new_id) fe_v = new_base + total_rec;
+            if (lane == 0) {
+                ctr_add(C_EXPANSIONS, ns);
+                ctr_add(C_NODE_STEPS, 1);
+                ctr_max(C_MAX_RECORDS, new_base + total_rec);
+            }
             wave_sync();
             // the new frame becomes the current one
-            f_id = new_id;
             f_base = new_base;
             f_nA = nA_tot;
-            f_ns = ns;
+            f_ns = n_pop;
             f_tasks = tasks_tot;
+            f_level = new_id;
+            f_meta = new_meta;
             have_frame = true;
         }
-        cnt.max_steps = max(cnt.max_steps, steps);
+        if (lane == 0) ctr_max(C_MAX_POSE_STEPS, steps);
         if (q.prio_steps && steps >= q.prio_steps) __builtin_amdgcn_s_setprio(0);
 
         // ---- results of this unit ----
@@ -1347,29 +1473,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     }
     // ---- this wave's counter row (plain stores: thousands of waves exit
     // at about the same time, and atomics on one line would serialise) ----
-    if (blockIdx.x == 0 && lane == 0) hdr->n_waves = gridDim.x;
+    if (wave_id == 0 && lane == 0) hdr->n_waves = n_waves;
     const unsigned long long t_exit = wall_clock64();
+    wave_sync();
     if (lane < (uint32_t)C_NUM) {
-        unsigned long long v = 0;
-        switch (lane) {
-        case C_BV_TESTS: v = cnt.bv_tests; break;
-        case C_TRI_TESTS: v = cnt.tri_tests; break;
-        case C_TRI_FP64: v = cnt.tri_fp64; break;
-        case C_EXPANSIONS: v = cnt.expansions; break;
-        case C_NODE_BYTES: v = cnt.node_bytes; break;
-        case C_TRI_BYTES: v = cnt.tri_bytes; break;
-        case C_DONATED: v = cnt.donated; break;
-        case C_MAX_ENTRIES: v = cnt.max_entries; break;
-        case C_MAX_RECORDS: v = cnt.max_records; break;
-        case C_T_START: v = t_first ? t_first : ~0ull; break;
-        case C_T_DRAIN: v = t_drain ? t_drain : ~0ull; break;
-        case C_T_END: v = t_exit; break;
-        case C_MAX_POSE_STEPS: v = cnt.max_steps; break;
-        case C_NODE_STEPS: v = cnt.node_steps; break;
-        case C_LEAF_STEPS: v = cnt.leaf_steps; break;
-        default: break;
-        }
-        q.ws.wave_ctr[(size_t)blockIdx.x * C_NUM + lane] = v;
+        unsigned long long v = ctr[lane];
+        if (lane == C_T_START) v = t_first ? t_first : ~0ull;
+        else if (lane == C_T_DRAIN) v = t_drain ? t_drain : ~0ull;
+        else if (lane == C_T_END) v = t_exit;
+        q.ws.wave_ctr[(size_t)wave_id * C_NUM + lane] = v;
     }
 }
 // ---------------------------------------------------------------------------
@@ -1641,7 +1753,7 @@ uint32_t env_u32(const char *name, uint32_t dflt)
 template <int K, int BITS, int MODE>
 hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
-    Layout L = make_layout(K, MODE, lim);
+    Layout L = make_layout(K, MODE, lim, (uint32_t)BITS);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1649,18 +1761,22 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // as many waves as fit on a CU at once (registers and LDS): the waves
     // are persistent, so every one of them must be resident
     int occ = 0;
+    // workgroup shape: waves per workgroup (independent waves; 1, 2 or 4)
+    uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", 1u);
+    wpg = wpg >= 4 ? 4u : wpg >= 2 ? 2u : 1u;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE>),
-                                                     WAVE, L.total) != hipSuccess || occ < 1) {
+                                                     WAVE * wpg, L.total * wpg) != hipSuccess || occ < 1) {
         (void)hipGetLastError();  // clear a failed query's error; fall back to the LDS bound
-        occ = (int)(160u * 1024u / (L.total + 256u));
+        occ = (int)(160u * 1024u / (L.total * wpg + 256u));
     }
-    uint32_t per_cu = min((uint32_t)occ, env_u32("CBVH_WAVES_PER_CU", 32u));
-    if (per_cu < 1) per_cu = 1;
+    uint32_t per_cu = min((uint32_t)occ * wpg, env_u32("CBVH_WAVES_PER_CU", 32u));
     if (per_cu > 32) per_cu = 32;
-    uint32_t grid = (uint32_t)cus * per_cu;
+    per_cu = max(per_cu / wpg, 1u) * wpg;
+    uint32_t waves = (uint32_t)cus * per_cu;
     // without donation a wave beyond the pose count has nothing to do
-    if (q.no_split && grid > q.n_poses) grid = q.n_poses;
-    if (grid > kMaxWaves) grid = kMaxWaves;  // rows of per-wave counters in the workspace
+    if (q.no_split && waves > q.n_poses) waves = q.n_poses;
+    if (waves > kMaxWaves) waves = kMaxWaves;  // rows of per-wave counters in the workspace
+    const uint32_t grid = (waves + wpg - 1) / wpg;  // (kMaxWaves is a multiple of every group size)
     {
         // workspace init: header (no pending work: each wave adds itself
         // when it starts), per-pose outputs, and the item queue's ready
@@ -1693,7 +1809,7 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // collision queries: units past 16 steps get issue priority (about 2 % on
     // the scaled workload); distance queries gain nothing from it
     qq.prio_steps = env_u32("CBVH_PRIO_STEPS", MODE == MODE_DIST ? 0u : 16u);
-    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE), L.total, s, qq, lim);
+    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE * wpg), L.total * wpg, s, qq, lim);
     return hipGetLastError();
 }
 
@@ -1750,7 +1866,10 @@ hipError_t static_workspace(void **out)
     return hipSuccess;
 }
 
-size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim) { return make_layout(K, mode, lim).total; }
+size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim, uint32_t bits)
+{
+    return make_layout(K, mode, lim, bits).total;
+}
 
 StackLimits default_limits(uint32_t K, int mode)
 {
@@ -1758,8 +1877,8 @@ StackLimits default_limits(uint32_t K, int mode)
     // the sizes let 10 waves (AABB) or 8 waves (18-DOP, the most its
     // registers allow) fit a CU, about 5 % faster than 8 and 7 waves with
     // the larger stacks used before (768 and 512 entries)
-    if (mode == MODE_DIST) return K == 9 ? StackLimits{144, 448, 128} : StackLimits{256, 512, 128};
-    return K == 9 ? StackLimits{80, 192, 128} : StackLimits{160, 384, 128};
+    if (mode == MODE_DIST) return K == 9 ? StackLimits{136, 448, 128} : StackLimits{256, 512, 128};
+    return K == 9 ? StackLimits{80, 160, 128} : StackLimits{160, 384, 128};
 }
 
 uint32_t item_words(uint32_t K) { return words_of_item(K); }

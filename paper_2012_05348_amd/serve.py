@@ -127,8 +127,11 @@ class Server:
     thousands of poses; the other slots admit any request, in arrival order."""
 
     def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
-                 memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None, small_max=256):
+                 memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None, small_max=256,
+                 launch_cfg=None):
         self.link, self.obstacles, self.device = link, obstacles, device
+        # launch knobs of a tuned configuration (autotune.launch_env), applied to every launch
+        self.launch_cfg = launch_cfg
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
             lo, hi = 4096, 1 << 22
@@ -155,6 +158,11 @@ class Server:
     def run(self, req: Requests, realtime=True):
         """Serve every request; returns per-request latencies (s), per-pose results
         (booleans and distances in request pose order) and throughput."""
+        from .autotune import launch_env
+        with launch_env(self.launch_cfg):
+            return self._run(req, realtime)
+
+    def _run(self, req, realtime):
         import torch
         R, N = len(req), len(req.poses)
         for k in (COLLIDE, DISTANCE):

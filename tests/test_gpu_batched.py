@@ -157,17 +157,29 @@ def test_batched_query_replays_from_a_hip_graph(setup):
         assert torch.equal(hit, eager)
 
 
-def test_autotuner_keeps_answers_and_picks_a_candidate(setup):
+def test_autotuner_keeps_answers_and_picks_a_candidate(setup, tmp_path):
     from paper_2012_05348_amd import autotune
     w, link_mesh, obs_meshes, link, obs, P, obj = setup
     n = 512
     res = autotune.tune(link_mesh, obs_meshes, P[:n], obj[:n], bits=w.bits, leaf_size=w.leaf_size,
-                        branchings=(4, 8), treelet_bytes=(8192,), waves_per_cu=(0, 8), steps=2, warmup=1,
-                        device=DEV)
-    assert len(res["results"]) == 4 and res["all_answers_equal"]
+                        branchings=(4, 8), treelet_bytes=(8192, autotune.WHOLE_TREE), waves_per_cu=(0, 8),
+                        waves_per_group=(1, 4), steps=2, warmup=1, device=DEV)
+    assert len(res["results"]) == 16 and res["all_answers_equal"]
     best = res["best"]
     assert best is not None and best["ms"] == min(r["ms"] for r in res["results"])
-    assert "CBVH_WAVES_PER_CU" not in os.environ
+    assert "CBVH_WAVES_PER_CU" not in os.environ and "CBVH_WAVES_PER_GROUP" not in os.environ
+    # the pick, stored and applied, answers like the default launch
+    path = autotune.save("test workload", best, str(tmp_path / "tune.json"))
+    cfg = autotune.load("test workload", path)
+    assert cfg == best
+    kw = dict(bv=cb.DOP18, leaf_size=w.leaf_size, bits=w.bits, **autotune.build_kwargs(cfg))
+    link2 = cb.Model.build(*link_mesh, **kw).to(DEV)
+    oset2 = cb.Obstacles([cb.Model.build(V, T, **kw).to(DEV) for V, T in obs_meshes], DEV)
+    Pd, od = torch.from_numpy(P[:n]).to(DEV), torch.from_numpy(obj[:n]).to(DEV)
+    ref, _ = cb.collide_batch(link, cb.Obstacles(obs, DEV), Pd, od)
+    with autotune.launch_env(cfg):
+        got, st = cb.collide_batch(link2, oset2, Pd, od)
+    assert (st.cpu().numpy() == 0).all() and torch.equal(got, ref)
 
 
 # ---------------------------------------------------------------- full size

@@ -548,3 +548,24 @@ def test_wait_limit_timeout_flags_every_pose(query):
         pos = ref > 0
         assert (got[~pos] == 0).all()
         assert (np.abs(got[pos] - ref[pos]) / ref[pos]).max() <= 1e-5
+
+
+@pytest.mark.parametrize("wpg", ["2", "4"])
+def test_workgroup_shape_keeps_answers(wpg, monkeypatch):
+    """Several independent waves per workgroup (the launch's workgroup shape,
+    a tuning knob) change how waves are placed, never an answer: collision
+    booleans of the scaled workload and distances of the proximity workload
+    equal the one-wave-per-workgroup launch bitwise."""
+    wc, wd = configs.WORKLOADS[1], configs.WORKLOADS[2]
+    Pc = torch.from_numpy(wc.raw_poses(4096)).to(DEV)
+    Pd = torch.from_numpy(wd.raw_poses(1024)).to(DEV)
+    mc, md = models(1), models(2)
+    ref_h, _ = cb.collide(*mc, Pc)
+    ref_d, _ = cb.distance(*md, Pd)
+    monkeypatch.setenv("CBVH_WAVES_PER_GROUP", wpg)
+    _log(f"workgroup shape: {wpg} waves per workgroup")
+    h, hs = cb.collide(*mc, Pc)
+    d, ds = cb.distance(*md, Pd)
+    assert (hs.cpu().numpy() == 0).all() and (ds.cpu().numpy() == 0).all()
+    assert torch.equal(h, ref_h)
+    assert torch.equal(d.view(torch.int32), ref_d.view(torch.int32))
