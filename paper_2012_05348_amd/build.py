@@ -13,9 +13,11 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("CBVH_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off", "-I" + os.path.join(HERE, "..", "include")]
-# device code: no packed-FP32 instruction selection; fp contraction only where written as fma
+# device code: no packed-FP32 instruction selection; fp contraction only where written as fma;
+# no atomic optimizer (every atomic in the kernels is issued by one lane, so its
+# cross-lane reduction code would only add instructions to the traversal loop)
 HIP = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-       "-munsafe-fp-atomics"]
+       "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 SOURCES = [("builder.cpp", False), ("capi.cpp", False), ("traverse.hip", True)]
 
 

@@ -123,7 +123,7 @@ __host__ __device__ constexpr uint32_t rec_words(uint32_t K) { return 2 * K + 2;
 __host__ __device__ constexpr bool topo_in_entry(int mode) { return mode != MODE_DIST; }
 
 struct Layout {
-    uint32_t ctr, xf, rec, ta, ta_topo, tsph, ent, ent_tp, ent_lb, lq, lq_lb, lscan, total;
+    uint32_t ctr, pz, xf, rec, ta, ta_topo, tsph, ent, ent_tp, ent_lb, lq, lq_lb, lscan, total;
 };
 
 __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim, uint32_t bits)
@@ -136,6 +136,7 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
         return r;
     };
     L.ctr = take(8 * C_NUM);
+    L.pz = take(64);
     L.xf = take(32 * K);
     L.rec = take(4 * rec_words(K) * lim.records);
     L.ta = (mode == MODE_DIST && K == 3) ? o : take(4 * rec_words(K) * TA_MAX);  // AABB distance tests read no transform
@@ -501,6 +502,19 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     constexpr uint32_t RV = RW / 4;        // float4 per record
     constexpr bool kTopoEnt = topo_in_entry(MODE);
     float4 *xf = (float4 *)(base + LY.xf);
+    // the current pose and its error allowances, kept in LDS (read where
+    // needed, so that they hold no scalar registers across the traversal):
+    // rows (R_i0, R_i1, R_i2, t_i), then (e_abs, e_sph, e_dir, rot_eps)
+    float4 *pz = (float4 *)(base + LY.pz);
+    auto pose_of = [&]() -> Pose {
+        Pose P;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const float4 r = pz[i];
+            P.R[3 * i] = r.x, P.R[3 * i + 1] = r.y, P.R[3 * i + 2] = r.z, P.t[i] = r.w;
+        }
+        return P;
+    };
     float *rec = (float *)(base + LY.rec);
     float *ta = (float *)(base + LY.ta);
     uint32_t *ta_topo = (uint32_t *)(base + LY.ta_topo);
@@ -522,7 +536,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     // this wave's statistics counters (C_* rows), kept in LDS so that they
     // hold no registers; lane 0 updates them with LDS atomics
     unsigned long long *ctr = (unsigned long long *)(base + LY.ctr);
-    if (lane < (uint32_t)C_NUM) ctr[lane] = 0;
+    if (lane < (uint32_t)C_NUM) ctr[lane] = (lane == C_T_START || lane == C_T_DRAIN) ? ~0ull : 0ull;
     auto ctr_add = [&](int c, unsigned long long v) {
         __hip_atomic_fetch_add(&ctr[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
@@ -533,7 +547,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     const uint32_t code_bytes_A = 4 + MA.stride;
     uint32_t code_bytes_B = 4 + MB.stride;
     const bool can_donate = !q.no_split;
-    unsigned long long t_first = 0, t_drain = ~0ull;
 
     // the two topology words of entry i
     auto entry_topo = [&](uint32_t i, uint32_t e) -> uint2 {
@@ -607,11 +620,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     // topology word beside the transformed records, and for AABB models or
     // distance queries its circumscribed sphere (centre placed by the pose)
     // and half extents in its own frame.
-    Pose P;
-    float rot_eps = 0.0f;
     auto prep_A = [&](uint32_t c, const float *b, uint32_t topo) {
         ta_topo[c] = topo;
         if constexpr (MODE == MODE_DIST || K == 3) {
+            const Pose P = pose_of();
+            const float rot_eps = pz[3].w;
             V3<float> cc = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
             float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
             // the map stretches lengths by at most 1 + 1.5 rot_eps
@@ -654,7 +667,6 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     const bool counted = can_donate && wave_id < q.n_poses;
     if (counted && lane == 0) rmw_add(&hdr->pending, 1u);
     uint32_t cur_pose = 0xFFFFFFFFu;
-    float e_abs = 0.0f, e_sph = 0.0f, e_dir = 0.0f;
     // this lane's slab (lane mod K) of the pose's support-function transform,
     // kept in registers for the whole pose
     const uint32_t my_k = lane % (uint32_t)K;
@@ -672,14 +684,16 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             // a wave's first pose is its block index; later ones come from
             // the queue (no burst of atomics on one line at the start)
             uint32_t p = wave_id;
-            if (!first_claim && lane == 0) p = n_waves + atomicAdd(&hdr->pose_next, 1u);
+            if (lane == 0) {
+                if (first_claim) ctr[C_T_START] = wall_clock64();
+                else p = n_waves + atomicAdd(&hdr->pose_next, 1u);
+            }
             first_claim = false;
             // (queue claims start at the grid size, past any block index)
             pose = uni(p);
-            if (t_first == 0) t_first = wall_clock64();
             if (pose >= q.n_poses) {
                 poses_left = false;
-                t_drain = wall_clock64();
+                if (lane == 0) ctr[C_T_DRAIN] = wall_clock64();
                 // this wave starts no more poses: it no longer counts as work
                 // that could still publish items
                 if (counted && lane == 0) rmw_add(&hdr->pending, 0xFFFFFFFFu);
@@ -764,38 +778,47 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 code_bytes_B = 4 + MB.stride;
             }
             cur_pose = pose;
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-#pragma unroll
-                for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
-                P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
-            }
-            pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, xf, lane);
-            // distance: FP32 leaf-distance error bound, and the absolute
-            // rounding allowance of the sphere bound
-            e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
-            e_sph = 64.0f * 0x1p-24f *
-                    (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
             {
-                // how far the rotation's columns are from orthonormal (their
-                // Gram matrix minus the identity, largest entry, in FP64):
-                // the gaps along A's axes below allow for it
-                double dev = 0.0;
+                Pose P;
 #pragma unroll
                 for (int i = 0; i < 3; i++) {
 #pragma unroll
-                    for (int j = i; j < 3; j++) {
-                        double g = 0.0;
-#pragma unroll
-                        for (int k = 0; k < 3; k++) g += (double)P.R[3 * k + i] * (double)P.R[3 * k + j];
-                        dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
-                    }
+                    for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
+                    P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
                 }
-                rot_eps = __double2float_ru(dev) + 0x1p-22f;
+                pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, xf, lane);
+                // distance: FP32 leaf-distance error bound, and the absolute
+                // rounding allowance of the sphere bound
+                const float e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
+                const float e_sph = 64.0f * 0x1p-24f *
+                                    (fabsf(P.t[0]) + fabsf(P.t[1]) + fabsf(P.t[2]) + 4.0f * (MA.max_abs + MB.max_abs));
+                float rot_eps;
+                {
+                    // how far the rotation's columns are from orthonormal (their
+                    // Gram matrix minus the identity, largest entry, in FP64):
+                    // the gaps along A's axes below allow for it
+                    double dev = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; i++) {
+#pragma unroll
+                        for (int j = i; j < 3; j++) {
+                            double g = 0.0;
+#pragma unroll
+                            for (int k = 0; k < 3; k++) g += (double)P.R[3 * k + i] * (double)P.R[3 * k + j];
+                            dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
+                        }
+                    }
+                    rot_eps = __double2float_ru(dev) + 0x1p-22f;
+                }
+                // rounding allowance of the directional gap below: the sphere
+                // bound's, grown with the matrix's largest stretch
+                const float e_dir = __builtin_fmaf(2.0f * rot_eps, e_sph, e_sph);
+                if (lane == 0) {
+#pragma unroll
+                    for (int i = 0; i < 3; i++) pz[i] = make_float4(P.R[3 * i], P.R[3 * i + 1], P.R[3 * i + 2], P.t[i]);
+                    pz[3] = make_float4(e_abs, e_sph, e_dir, rot_eps);
+                }
             }
-            // rounding allowance of the directional gap below: the sphere
-            // bound's, grown with the matrix's largest stretch
-            e_dir = __builtin_fmaf(2.0f * rot_eps, e_sph, e_sph);
             wave_sync();
             // this lane's slab of the support-function transform
             const float4 x0 = xf[2 * my_k], x1 = xf[2 * my_k + 1];
@@ -900,7 +923,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     wave_sync();
                 }
                 // -------- child-pair tests, one per lane --------
-                const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
+                const float tau = MODE == MODE_DIST ? add_up(best32, pz[3].x) : 0.0f;
                 bool survive = false;
                 float lb = 0.0f;
                 uint32_t recA = 0, recB = 0, tA_w = 0, tB_w = 0;
@@ -962,10 +985,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
                         const float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
                         const float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
-                        const float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - e_sph;
+                        const float4 ez = pz[3];
+                        const float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - ez.y;
                         // third lower bound: the gap along one well-chosen direction
                         // (gaps along A's own axes, tried beside it, pruned no more)
-                        const float gd = dir_gap(P.R, sa, tsph[2 * ia + 1], bB, dx, dy, dz, hx, hy, hz, e_dir);
+                        const Pose P = pose_of();
+                        const float gd = dir_gap(P.R, sa, tsph[2 * ia + 1], bB, dx, dy, dz, hx, hy, hz, ez.z);
                         lb = fmaxf(fmaxf(g * (1.0f - 0x1p-20f), gs), gd);  // g is -inf for AABB models
                         survive = lb <= tau;
                     } else {
@@ -1000,6 +1025,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                         dz = 0.5f * (bB[4] + bB[5]) - sa.z;
                             const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]),
                                         hz = 0.5f * (bB[5] - bB[4]);
+                            const Pose P = pose_of();
+                            const float4 ez = pz[3];
                             float ga = -INFINITY;
 #pragma unroll
                             for (int a = 0; a < 3; a++) {
@@ -1009,7 +1036,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                     __builtin_fmaf(fabsf(c0), hx, __builtin_fmaf(fabsf(c1), hy, fabsf(c2) * hz));
                                 ga = fmaxf(ga, fabsf(p) - (a == 0 ? ea.x : a == 1 ? ea.y : ea.z) - rbi);
                             }
-                            ga = __builtin_fmaf(-rot_eps, ea.w, ga) * (1.0f - 0x1p-20f - rot_eps) - e_sph;
+                            ga = __builtin_fmaf(-ez.w, ea.w, ga) * (1.0f - 0x1p-20f - ez.w) - ez.y;
                             sep |= ga > 0.0f;
                         }
                         survive = !sep;
@@ -1078,6 +1105,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             if (screen) trig = min(trig * kScreenTrigMult, lim.leafq / 2u);
             if (MODE == MODE_DIST && best32 == INFINITY) trig = 1;
             if (lq_count > 0 && (lq_count >= trig || top == 0)) {
+                const Pose P = pose_of();
+                const float e_abs = pz[3].x;
                 const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
                 uint32_t n_avail = min(lq_count, (uint32_t)WAVE);
                 uint32_t tasks = 0;
@@ -1292,7 +1321,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
 
 
             // -------- node step: pop the top entries whose children fit one decode pass --------
-            const float tau = MODE == MODE_DIST ? add_up(best32, e_abs) : 0.0f;
+            const float tau = MODE == MODE_DIST ? add_up(best32, pz[3].x) : 0.0f;
             // lane l <= PMAX reads the (l+1)-th entry from the top, with both
             // topology words (collision queries keep them in the entry)
             uint32_t my_e = 0, my_tA = 0, my_tB = 0, my_na = 0, my_nb = 0;
@@ -1478,9 +1507,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     wave_sync();
     if (lane < (uint32_t)C_NUM) {
         unsigned long long v = ctr[lane];
-        if (lane == C_T_START) v = t_first ? t_first : ~0ull;
-        else if (lane == C_T_DRAIN) v = t_drain ? t_drain : ~0ull;
-        else if (lane == C_T_END) v = t_exit;
+        if (lane == C_T_END) v = t_exit;
         q.ws.wave_ctr[(size_t)wave_id * C_NUM + lane] = v;
     }
 }
