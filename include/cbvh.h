@@ -53,7 +53,15 @@ typedef enum {
     CBVH_E_FORMAT = 6       /* a serialized model failed validation */
 } cbvh_status;
 
-typedef enum { CBVH_AABB = 0, CBVH_DOP18 = 1 } cbvh_bv;
+/* BV types.  CBVH_OBB (oriented boxes, named among the BV types of the
+ * paper's section I and as future work for this layout in section V): an
+ * absolute node stores its own frame (origin and three float32 axes from a
+ * principal-axis fit of its triangles) and three frame-coordinate intervals;
+ * relative nodes keep their parent's frame and code their intervals against
+ * the parent's like the fixed slabs of the other types.  Frames change only
+ * at absolute nodes (treelet tops; every node when bits == 0).  OBB models
+ * take bits 0, 8 or 16. */
+typedef enum { CBVH_AABB = 0, CBVH_DOP18 = 1, CBVH_OBB = 2 } cbvh_bv;
 
 /* `bits` value selecting absolute binary16 descriptors, each bound rounded
  * outward (lo down, hi up): the half-precision BVs of section III.A of the
@@ -65,7 +73,7 @@ typedef enum { CBVH_AABB = 0, CBVH_DOP18 = 1 } cbvh_bv;
  * (AABB 6 floats, k-DOP k floats); `bits` selects the quantized width. */
 typedef struct {
     uint32_t size;          /* = sizeof(cbvh_build_params) */
-    uint32_t bv;            /* CBVH_AABB (3 slabs) or CBVH_DOP18 (9 slabs) */
+    uint32_t bv;            /* CBVH_AABB (3 slabs), CBVH_DOP18 (9 slabs) or CBVH_OBB (3 slabs in a frame) */
     uint32_t branching;     /* children per inner node: 2, 4 or 8 */
     uint32_t leaf_size;     /* triangles per leaf: 1..8 */
     uint32_t bits;          /* 0 = FP32 descriptors (uncompressed), 8 or 16 = quantized codes,
@@ -239,7 +247,9 @@ cbvh_status cbvh_distance_batch(const cbvh_model *a, const void *a_dev, const cb
                                 void *stream);
 
 /* Decode every node's bounds on the device: out = device float32
- * [n_nodes][2*slabs] as (lo, hi) per slab.  Parity tool for the decoder. */
+ * [n_nodes][2*slabs] as (lo, hi) per slab; OBB models: [n_nodes][20], each
+ * node's whole descriptor (lo0 hi0 lo1 hi1 lo2 hi2, 0, eps, origin, three
+ * axes).  Parity tool for the decoder. */
 cbvh_status cbvh_decode_all(const cbvh_model *m, const void *m_dev, float *out, void *stream);
 
 /* Counters of the last query that used this workspace.  Synchronizes

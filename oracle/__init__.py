@@ -235,10 +235,12 @@ def blob_info(blob: bytes):
 
 
 def blob_decode(blob: bytes):
-    """Decoded float32 bounds of every node, shape (n_nodes, 2K), (lo, hi) per slab."""
+    """Decoded float32 bounds of every node, shape (n_nodes, 2K), (lo, hi) per slab;
+    OBB blobs (bv 2): shape (n_nodes, 20), each node's descriptor with its frame."""
     info = blob_info(blob)
     b = np.frombuffer(blob, dtype=np.uint8)
-    out = np.zeros((info["n_nodes"], 2 * info["K"]), dtype=np.float32)
+    width = 20 if info["bv"] == 2 else 2 * info["K"]
+    out = np.zeros((info["n_nodes"], width), dtype=np.float32)
     msg = C.create_string_buffer(256)
     if lib().orc_blob_decode(_p(b), len(b), _p(out), msg, 256) != 0:
         raise ValueError(msg.value.decode())

@@ -874,6 +874,14 @@ EXPORT void orc_classify_batch(const void *A, const void *B, const float *poses,
  *     binary16 (the half-precision descriptors of section III.A of the
  *     paper, rounded outward).  Absolute nodes keep a u32 index into abs.
  *   abs[n_abs][2K]: f32 (lo, hi) per slab.
+ *   Oriented boxes (bv 2, K 3; the OBBs the paper names among BV types and
+ *     as future work for its layout): a node is {o + u0 a0 + u1 a1 + u2 a2 :
+ *     lo_k <= u_k <= hi_k}, its slabs the intervals of the frame
+ *     coordinates u.  Its descriptor is 20 f32: lo0 hi0 lo1 hi1 lo2 hi2, 0,
+ *     eps, o[3], a0[3], a1[3], a2[3], with eps >= max |a_i.a_j - [i==j]|.
+ *     Absolute nodes (all nodes when bits = 0) store the whole descriptor
+ *     (abs[] entries, or the code slot: stride 80); relative nodes code their
+ *     intervals against the parent's like fixed slabs and keep its frame.
  *   tris[n_tris][9]: f32 in leaf order;  perm[n_tris]: u32 input index.
  *   treelets[n_treelets+1]: u32 first node of each treelet.
  * Decoding a relative node from its decoded parent interval [Pl, Ph] with
@@ -905,6 +913,10 @@ static float half_value(uint16_t h)
 static uint16_t half_next_up(uint16_t h) { return h == 0x8000 ? 0x0001 : (h & 0x8000) ? (uint16_t)(h - 1) : (uint16_t)(h + 1); }
 static uint16_t half_next_down(uint16_t h) { return h == 0x0000 ? 0x8001 : (h & 0x8000) ? (uint16_t)(h + 1) : (uint16_t)(h - 1); }
 
+/* f32 words per decoded node: the bounds, or an OBB's whole descriptor */
+#define OBB_WORDS 20
+static uint32_t desc_words(const ohdr_t *h) { return h->bv == 2 ? OBB_WORDS : 2 * h->K; }
+
 static int parse_header(const uint8_t *blob, size_t n, ohdr_t *h, char *msg, size_t ml)
 {
     if (n < 128 || memcmp(blob, "CBVH", 4) != 0) { snprintf(msg, ml, "bad magic/size"); return -1; }
@@ -914,14 +926,15 @@ static int parse_header(const uint8_t *blob, size_t n, ohdr_t *h, char *msg, siz
     h->n_treelets = rd32(blob + 40); h->code_stride = rd32(blob + 44); h->depth = rd32(blob + 48); h->treelet_bytes = rd32(blob + 52);
     h->off_topo = rd64(blob + 56); h->off_codes = rd64(blob + 64); h->off_abs = rd64(blob + 72); h->off_tris = rd64(blob + 80);
     h->off_perm = rd64(blob + 88); h->off_treelets = rd64(blob + 96); h->total = rd64(blob + 104); h->max_abs_coord = rdf32(blob + 112);
-    if (!((h->bv == 0 && h->K == 3) || (h->bv == 1 && h->K == 9))) { snprintf(msg, ml, "bad bv/K"); return -1; }
+    if (!((h->bv == 0 && h->K == 3) || (h->bv == 1 && h->K == 9) || (h->bv == 2 && h->K == 3))) { snprintf(msg, ml, "bad bv/K"); return -1; }
     if (!(h->bits == 0 || bits_codes(h->bits) || h->bits == BITS_FP16)) { snprintf(msg, ml, "bad bits"); return -1; }
-    uint32_t want = h->bits == 0 ? 8 * h->K : h->bits == BITS_FP16 ? 4 * h->K : (h->bits / 8) * 2 * h->K;
+    if (h->bv == 2 && h->bits == BITS_FP16) { snprintf(msg, ml, "FP16 OBB blob"); return -1; }
+    uint32_t want = h->bits == 0 ? (h->bv == 2 ? 80 : 8 * h->K) : h->bits == BITS_FP16 ? 4 * h->K : (h->bits / 8) * 2 * h->K;
     if (h->code_stride != want) { snprintf(msg, ml, "bad code stride"); return -1; }
     if (h->total != n) { snprintf(msg, ml, "size mismatch"); return -1; }
 #define FITS(off, bytes) ((off) <= n && (uint64_t)(bytes) <= n - (off))
     if (!FITS(h->off_topo, 4ull * h->n_nodes) || !FITS(h->off_codes, (uint64_t)h->code_stride * h->n_nodes) ||
-        !FITS(h->off_abs, 8ull * h->K * h->n_abs) || !FITS(h->off_tris, 36ull * h->n_tris) ||
+        !FITS(h->off_abs, 4ull * desc_words(h) * h->n_abs) || !FITS(h->off_tris, 36ull * h->n_tris) ||
         !FITS(h->off_perm, 4ull * h->n_tris) || !FITS(h->off_treelets, 4ull * (h->n_treelets + 1))) {
         snprintf(msg, ml, "section out of range"); return -1;
     }
@@ -929,10 +942,11 @@ static int parse_header(const uint8_t *blob, size_t n, ohdr_t *h, char *msg, siz
     return 0;
 }
 
-/* decode every node's bounds, top-down; out[n][2K] as (lo, hi) per slab */
+/* decode every node's bounds, top-down; out[n][2K] as (lo, hi) per slab
+ * (OBB blobs: out[n][20], each node's descriptor with its frame) */
 static int decode_all(const uint8_t *blob, const ohdr_t *h, float *out, int32_t *parent, char *msg, size_t ml)
 {
-    const uint32_t K2 = 2 * h->K;
+    const uint32_t K2 = 2 * h->K, DW = desc_words(h);
     for (uint32_t i = 0; i < h->n_nodes; i++) parent[i] = -2;
     parent[0] = -1;
     for (uint32_t i = 0; i < h->n_nodes; i++) {
@@ -940,22 +954,24 @@ static int decode_all(const uint8_t *blob, const ohdr_t *h, float *out, int32_t 
         const uint8_t *code = blob + h->off_codes + (uint64_t)h->code_stride * i;
         if (parent[i] == -2) { snprintf(msg, ml, "node %u unreachable or out of order", i); return -1; }
         int absolute = (tw >> 30) & 1;
+        float *o = &out[DW * (size_t)i];
         if (h->bits == 0) {
-            for (uint32_t k = 0; k < K2; k++) out[K2 * (size_t)i + k] = rdf32(code + 4 * k);
+            for (uint32_t k = 0; k < DW; k++) o[k] = rdf32(code + 4 * k);
         } else if (h->bits == BITS_FP16) {
             if (absolute) { snprintf(msg, ml, "absolute flag in an FP16 blob"); return -1; }
             for (uint32_t k = 0; k < K2; k++) {
                 uint16_t hv = rd16(code + 2 * k);
                 if (!half_finite(hv)) { snprintf(msg, ml, "non-finite FP16 bound at node %u", i); return -1; }
-                out[K2 * (size_t)i + k] = half_value(hv);
+                o[k] = half_value(hv);
             }
         } else if (absolute || parent[i] < 0) {
             if (!absolute) { snprintf(msg, ml, "root not absolute"); return -1; }
             uint32_t ai = rd32(code);
             if (ai >= h->n_abs) { snprintf(msg, ml, "abs index out of range"); return -1; }
-            for (uint32_t k = 0; k < K2; k++) out[K2 * (size_t)i + k] = rdf32(blob + h->off_abs + 4ull * (K2 * (size_t)ai + k));
+            for (uint32_t k = 0; k < DW; k++) o[k] = rdf32(blob + h->off_abs + 4ull * (DW * (size_t)ai + k));
         } else {
-            const float *P = &out[K2 * (size_t)parent[i]];
+            const float *P = &out[DW * (size_t)parent[i]];
+            for (uint32_t k = K2; k < DW; k++) o[k] = P[k]; /* an OBB keeps its parent's frame */
             for (uint32_t k = 0; k < h->K; k++) {
                 uint32_t ql, qh;
                 if (h->bits == 8) { ql = code[2 * k]; qh = code[2 * k + 1]; }
@@ -963,8 +979,8 @@ static int decode_all(const uint8_t *blob, const ohdr_t *h, float *out, int32_t 
                 float Pl = P[2 * k], Ph = P[2 * k + 1];
                 float E = Ph - Pl;
                 float s = (E >= 0x1p-100f) ? ldexpf(E, -(int)h->bits) : 0.0f;
-                out[K2 * (size_t)i + 2 * k] = fmaf((float)ql, s, Pl);
-                out[K2 * (size_t)i + 2 * k + 1] = fmaf(-(float)qh, s, Ph);
+                o[2 * k] = fmaf((float)ql, s, Pl);
+                o[2 * k + 1] = fmaf(-(float)qh, s, Ph);
             }
         }
         if (!((tw >> 31) & 1)) {
@@ -1033,6 +1049,92 @@ static dd_t slab_value(const float *p, int k)
     }
 }
 
+/* Frame coordinates of x in the frame (o, a0, a1, a2): the solution of
+ * u0 a0 + u1 a1 + u2 a2 = x - o by Cramer's rule in FP64.  Returns a bound
+ * on the evaluation's error (for axes within 2^-6 of orthonormal the
+ * determinant is near 1 and every rounding is relative to |x - o|). */
+static double frame_coords(const float *f, const double *x, double *u)
+{
+    double a[3][3], d[3];
+    for (int j = 0; j < 3; j++)
+        for (int k = 0; k < 3; k++) a[j][k] = f[11 + 3 * j + k];
+    for (int k = 0; k < 3; k++) d[k] = x[k] - (double)f[8 + k];
+    double det;
+    {
+        double c[3];
+        vcross(a[1], a[2], c);
+        det = vdot(a[0], c);
+    }
+    double c12[3], c20[3], c01[3];
+    vcross(a[1], a[2], c12);
+    vcross(a[2], a[0], c20);
+    vcross(a[0], a[1], c01);
+    u[0] = vdot(d, c12) / det;
+    u[1] = vdot(d, c20) / det;
+    u[2] = vdot(d, c01) / det;
+    return 0x1p-44 * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
+}
+
+/* OBB blob invariants: every frame's eps bounds its axes' orthonormality
+ * defect (and is below 2^-6); every node's intervals are ordered, lie in its
+ * parent's where the two share a frame, and enclose the frame coordinates of
+ * every vertex of the node's triangles (beyond the FP64 evaluation error). */
+static int obb_check(const uint8_t *blob, const ohdr_t *h, const float *dec, const int32_t *parent, char *msg,
+                     size_t ml)
+{
+    uint32_t *stack = malloc(sizeof(uint32_t) * (h->n_nodes + 1));
+    int rc = -1;
+    for (uint32_t i = 0; i < h->n_nodes; i++) {
+        const float *f = &dec[OBB_WORDS * (size_t)i];
+        uint32_t tw = rd32(blob + h->off_topo + 4ull * i);
+        int absolute = (tw >> 30) & 1;
+        for (int k = 7; k < OBB_WORDS; k++)
+            if (!isfinite(f[k])) { snprintf(msg, ml, "node %u frame not finite", i); goto out; }
+        double defect = 0.0;
+        for (int p = 0; p < 3; p++)
+            for (int q = p; q < 3; q++) {
+                double g = 0.0;
+                for (int k = 0; k < 3; k++) g += (double)f[11 + 3 * p + k] * (double)f[11 + 3 * q + k];
+                defect = dmax(defect, fabs(g - (p == q ? 1.0 : 0.0)));
+            }
+        if (!((double)f[7] >= defect + 0x1p-50) || f[7] > 0x1p-6f) { snprintf(msg, ml, "node %u eps does not bound its frame", i); goto out; }
+        for (int k = 0; k < 3; k++)
+            if (!(f[2 * k] <= f[2 * k + 1])) { snprintf(msg, ml, "node %u slab %d empty", i, k); goto out; }
+        int same_frame = parent[i] >= 0 && bits_codes(h->bits) && !absolute;
+        if (same_frame) {
+            const float *P = &dec[OBB_WORDS * (size_t)parent[i]];
+            for (int k = 0; k < 3; k++)
+                if (f[2 * k] < P[2 * k] || f[2 * k + 1] > P[2 * k + 1]) { snprintf(msg, ml, "node %u slab %d outside parent", i, k); goto out; }
+        }
+        /* every vertex under the node */
+        uint32_t sp = 0;
+        stack[sp++] = i;
+        while (sp) {
+            uint32_t x = stack[--sp], w = rd32(blob + h->off_topo + 4ull * x);
+            uint32_t first = w & 0x07FFFFFFu, cnt = ((w >> 27) & 7u) + 1;
+            if (!((w >> 31) & 1)) {
+                for (uint32_t c = 0; c < cnt; c++) stack[sp++] = first + c;
+                continue;
+            }
+            for (uint32_t t = first; t < first + cnt; t++)
+                for (int v = 0; v < 3; v++) {
+                    double p[3], u[3];
+                    for (int c = 0; c < 3; c++) p[c] = rdf32(blob + h->off_tris + 4ull * (9 * (size_t)t + 3 * v + c));
+                    double e = frame_coords(f, p, u);
+                    for (int k = 0; k < 3; k++)
+                        if (!((double)f[2 * k] <= u[k] - e && u[k] + e <= (double)f[2 * k + 1])) {
+                            snprintf(msg, ml, "node %u slab %d does not enclose triangle %u", i, k, t);
+                            goto out;
+                        }
+                }
+        }
+    }
+    rc = 0;
+out:
+    free(stack);
+    return rc;
+}
+
 /* Invariant check of a blob against the mesh it was built from:
  *  (1) leaf-order triangles equal the input triangles under perm, perm is a
  *      permutation and the leaves' triangle ranges partition it;
@@ -1050,7 +1152,7 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
     if (h.n_tris != nt) { snprintf(msg, ml, "triangle count mismatch"); return -1; }
     const uint32_t K2 = 2 * h.K;
     int rc = -1;
-    float *dec = malloc(sizeof(float) * K2 * (size_t)h.n_nodes);
+    float *dec = malloc(sizeof(float) * desc_words(&h) * (size_t)h.n_nodes);
     int32_t *parent = malloc(sizeof(int32_t) * h.n_nodes);
     dd_t *exlo = malloc(sizeof(dd_t) * h.K * (size_t)h.n_nodes), *exhi = malloc(sizeof(dd_t) * h.K * (size_t)h.n_nodes);
     uint8_t *seen = calloc(nt, 1);
@@ -1106,6 +1208,11 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
         }
     }
     for (uint32_t t = 0; t < nt; t++) if (!seen[t]) { snprintf(msg, ml, "triangle %u in no leaf", t); goto done; }
+    if (h.bv == 2) {
+        /* oriented boxes: frames, enclosure in frame coordinates, nesting */
+        if (obb_check(blob, &h, dec, parent, msg, ml)) goto done;
+        goto treelets;
+    }
     /* (2)-(4) */
     for (uint32_t i = 0; i < h.n_nodes; i++) {
         uint32_t tw = rd32(blob + h.off_topo + 4ull * i);
@@ -1141,6 +1248,7 @@ EXPORT int orc_blob_check(const uint8_t *blob, size_t n, const float *V, uint32_
         }
     }
     /* (5) treelets */
+treelets:
     {
         uint32_t prev = 0;
         if (h.n_treelets < 1 || rd32(blob + h.off_treelets) != 0 || rd32(blob + h.off_treelets + 4ull * h.n_treelets) != h.n_nodes) {

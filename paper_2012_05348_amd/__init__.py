@@ -21,7 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbvh.so")
 
-AABB, DOP18 = 0, 1
+AABB, DOP18, OBB = 0, 1, 2
+# words of an OBB descriptor: lo0 hi0 lo1 hi1 lo2 hi2, 0, eps, origin[3], axes[3][3]
+OBB_WORDS = 20
 BITS_FP16 = 0x8010  # half-precision absolute descriptors (CBVH_BITS_FP16)
 EARLY_EXIT, PAIRS, NO_SPLIT = 0x1, 0x2, 0x4
 POSE_OK, POSE_STACK_OVERFLOW, POSE_PAIR_OVERFLOW, POSE_FP64_OVERFLOW, POSE_BAD_OBSTACLE, POSE_INCOMPLETE = range(6)
@@ -285,7 +287,8 @@ class Model:
     def decode_all(self):
         import torch
         info = self.info()
-        out = torch.empty((info["n_nodes"], 2 * info["slabs"]), dtype=torch.float32, device=self.dev.device)
+        width = OBB_WORDS if info["bv"] == OBB else 2 * info["slabs"]
+        out = torch.empty((info["n_nodes"], width), dtype=torch.float32, device=self.dev.device)
         cbvh_decode_all(self._h, self.dev, out)
         return out
 

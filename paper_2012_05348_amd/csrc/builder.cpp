@@ -71,7 +71,7 @@ float round_up(const Exact &v)
 
 struct TmpNode {
     bool leaf = false;
-    uint32_t begin = 0, end = 0;     // triangle range in `order` (leaves)
+    uint32_t begin = 0, end = 0;     // triangle range of the subtree in `order`
     std::vector<uint32_t> children;  // indices into the temporary node array
     uint32_t depth = 0;
     Exact lo[9], hi[9];
@@ -85,7 +85,7 @@ struct Builder {
     std::vector<uint32_t> order;     // triangle indices; leaves own contiguous ranges
     std::vector<TmpNode> nodes;
 
-    explicit Builder(const BuildParams &pp) : p(pp), K(pp.bv == 0 ? 3 : 9) {}
+    explicit Builder(const BuildParams &pp) : p(pp), K(bv_slabs(pp.bv)) {}
 
     // one binary median split of order[b, e): longest axis of the centroid
     // bounds, sort by (centroid, input index), left part keeps full leaves
@@ -116,10 +116,10 @@ struct Builder {
         uint32_t me = (uint32_t)nodes.size();
         nodes.emplace_back();
         nodes[me].depth = depth;
+        nodes[me].begin = b;
+        nodes[me].end = e;
         if (e - b <= p.leaf_size) {
             nodes[me].leaf = true;
-            nodes[me].begin = b;
-            nodes[me].end = e;
             return me;
         }
         std::vector<std::pair<uint32_t, uint32_t>> parts{{b, e}};
@@ -168,6 +168,158 @@ struct Builder {
         }
     }
 };
+
+// ---- oriented boxes ----
+// A frame: origin o and axes a[k] (float32, the values the descriptor
+// stores), eps >= max |a_i . a_j - [i == j]|, and M^-1 (FP64) for the
+// frame coordinates u = M^-1 (x - o), M = [a0 a1 a2] by columns.
+struct Frame {
+    float o[3], a[3][3], eps;
+    double inv[3][3];
+    double pad;  // outward pad of every interval coded in this frame
+};
+
+// eigenvectors of a symmetric 3x3 matrix (cyclic Jacobi rotations), as the
+// rows of V, ordered by decreasing eigenvalue
+void sym_eigen3(double A[3][3], double V[3][3])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 64; sweep++) {
+        double off = std::fabs(A[0][1]) + std::fabs(A[0][2]) + std::fabs(A[1][2]);
+        double scale = std::fabs(A[0][0]) + std::fabs(A[1][1]) + std::fabs(A[2][2]);
+        if (off <= 1e-30 * scale || off == 0.0) break;
+        for (int p = 0; p < 2; p++)
+            for (int q = p + 1; q < 3; q++) {
+                if (A[p][q] == 0.0) continue;
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < 3; k++) {  // A <- J^T A J
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - sn * akq;
+                    A[k][q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 3; k++) {
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - sn * aqk;
+                    A[q][k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 3; k++) {  // rows of V are eigenvectors
+                    double vp = V[p][k], vq = V[q][k];
+                    V[p][k] = c * vp - sn * vq;
+                    V[q][k] = sn * vp + c * vq;
+                }
+            }
+    }
+    int ord[3] = {0, 1, 2};
+    std::sort(ord, ord + 3, [&](int x, int y) { return A[x][x] > A[y][y] || (A[x][x] == A[y][y] && x < y); });
+    double W[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) W[i][k] = V[ord[i]][k];
+    memcpy(V, W, sizeof W);
+}
+
+// largest float <= x, smallest float >= x (x a double)
+float f32_down(double x)
+{
+    float f = (float)x;
+    while ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+float f32_up(double x)
+{
+    float f = (float)x;
+    while ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+// The frame of an absolute OBB node: principal axes of the vertices of its
+// triangles (order[b, e) of the builder), origin at their mean.
+Frame fit_frame(const std::vector<float> &tri, const std::vector<uint32_t> &order, uint32_t b, uint32_t e)
+{
+    double mean[3] = {0, 0, 0};
+    const double nv = 3.0 * (double)(e - b);
+    for (uint32_t i = b; i < e; i++)
+        for (int v = 0; v < 3; v++)
+            for (int k = 0; k < 3; k++) mean[k] += tri[9 * (size_t)order[i] + 3 * v + k];
+    for (int k = 0; k < 3; k++) mean[k] /= nv;
+    double C[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (uint32_t i = b; i < e; i++)
+        for (int v = 0; v < 3; v++) {
+            double d[3];
+            for (int k = 0; k < 3; k++) d[k] = tri[9 * (size_t)order[i] + 3 * v + k] - mean[k];
+            for (int r = 0; r < 3; r++)
+                for (int c = 0; c < 3; c++) C[r][c] += d[r] * d[c];
+        }
+    double V[3][3];
+    sym_eigen3(C, V);
+    // a right-handed frame (the third axis the cross product of the first two)
+    V[2][0] = V[0][1] * V[1][2] - V[0][2] * V[1][1];
+    V[2][1] = V[0][2] * V[1][0] - V[0][0] * V[1][2];
+    V[2][2] = V[0][0] * V[1][1] - V[0][1] * V[1][0];
+    Frame f;
+    for (int k = 0; k < 3; k++) f.o[k] = (float)mean[k];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) f.a[i][k] = (float)V[i][k];
+    // orthonormality defect of the stored axes (products of floats are exact
+    // in FP64; the two additions of each entry round by at most 2^-52 of 3)
+    double dev = 0.0;
+    for (int i = 0; i < 3; i++)
+        for (int j = i; j < 3; j++) {
+            double g = 0.0;
+            for (int k = 0; k < 3; k++) g += (double)f.a[i][k] * (double)f.a[j][k];
+            dev = std::max(dev, std::fabs(g - (i == j ? 1.0 : 0.0)));
+        }
+    f.eps = f32_up(dev + 0x1p-48);
+    // M^-1 = adj(M) / det(M), M[r][c] = a[c][r]
+    double M[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) M[r][c] = f.a[c][r];
+    double adj[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+            adj[r][c] = M[r1][c1] * M[r2][c2] - M[r1][c2] * M[r2][c1];
+        }
+    double det = M[0][0] * adj[0][0] + M[0][1] * adj[1][0] + M[0][2] * adj[2][0];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) f.inv[r][c] = adj[r][c] / det;
+    // the FP64 evaluation of u (a few roundings of terms bounded by |x - o|
+    // times entries of M^-1 near 1) errs by far less than 2^-40 |x - o|_1:
+    // intervals are widened by that much, the same in every node of the frame
+    double ext = 0.0;
+    for (uint32_t i = b; i < e; i++)
+        for (int v = 0; v < 3; v++) {
+            double s1 = 0.0;
+            for (int k = 0; k < 3; k++) s1 += std::fabs((double)tri[9 * (size_t)order[i] + 3 * v + k] - (double)f.o[k]);
+            ext = std::max(ext, s1);
+        }
+    f.pad = 0x1p-40 * ext + 0x1p-1000;
+    return f;
+}
+
+// frame-coordinate intervals of the vertices of order[b, e), widened by the
+// frame's pad
+void frame_bounds(const Frame &f, const std::vector<float> &tri, const std::vector<uint32_t> &order, uint32_t b,
+                  uint32_t e, Exact lo[3], Exact hi[3])
+{
+    double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = b; i < e; i++)
+        for (int v = 0; v < 3; v++) {
+            double d[3];
+            for (int k = 0; k < 3; k++) d[k] = (double)tri[9 * (size_t)order[i] + 3 * v + k] - (double)f.o[k];
+            for (int k = 0; k < 3; k++) {
+                double u = f.inv[k][0] * d[0] + f.inv[k][1] * d[1] + f.inv[k][2] * d[2];
+                l[k] = std::min(l[k], u);
+                h[k] = std::max(h[k], u);
+            }
+        }
+    for (int k = 0; k < 3; k++) {
+        lo[k] = {l[k] - f.pad, 0.0};
+        hi[k] = {h[k] + f.pad, 0.0};
+    }
+}
 
 // binary16 helpers for the half-precision descriptors: finite halves in
 // value order are ranks 0 .. 2*0x7C00-1 (negatives from -65504 up to -0,
@@ -262,9 +414,11 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
     std::iota(B.order.begin(), B.order.end(), 0u);
     B.nodes.reserve(2 * (size_t)nt / std::max(1u, p.leaf_size) + 8);
     B.build(0, nt, 0);
-    B.exact_slabs(0);
+    const bool obb = p.bv == kBvObb;
+    if (obb && !(p.bits == 0 || bits_are_codes(p.bits))) return "OBB models take bits 0, 8 or 16";
+    if (!obb) B.exact_slabs(0);
 
-    const uint32_t stride = code_stride_for(K, p.bits);
+    const uint32_t stride = code_stride_for(K, p.bits, p.bv);
     const uint32_t n_nodes = (uint32_t)B.nodes.size();
     if (n_nodes > kIndexMask) return "too many nodes";
 
@@ -279,7 +433,7 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
     const bool codes_mode = bits_are_codes(p.bits);
     if (p.bits == kBitsFp16 && max_abs * (K == 9 ? 2.0f : 1.0f) >= 32768.0f)
         return "FP16 descriptors need |coordinate| < 32768 (16384 for 18-DOPs)";
-    const uint64_t abs_node = codes_mode ? 4 + stride + 8 * (uint64_t)K : 4 + stride;
+    const uint64_t abs_node = codes_mode ? 4 + stride + 4 * (uint64_t)abs_words(K, p.bv) : 4 + stride;
     std::vector<std::vector<uint32_t>> groups;   // node ids per group, breadth-first
     std::vector<std::vector<uint32_t>> kids;     // child groups of each group
     groups.push_back({0u});
@@ -371,9 +525,40 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
         }
     }
 
+    // ---- oriented boxes: frames of the absolute nodes (every node without
+    // codes), inherited by relative nodes; intervals in the node's frame ----
+    std::vector<uint32_t> frame_of(obb ? n_nodes : 0);
+    std::vector<Frame> frames;
+    if (obb) {
+        for (uint32_t i = 0; i < n_nodes; i++) {
+            TmpNode &nd = B.nodes[oldid[i]];
+            if (p.bits == 0 || topo_abs(topo[i])) {
+                frame_of[i] = (uint32_t)frames.size();
+                frames.push_back(fit_frame(B.tri, B.order, nd.begin, nd.end));
+            } else if (i == 0) {
+                return "internal error: relative root";
+            }
+            if (!topo_leaf(topo[i]))
+                for (uint32_t c = 0; c < topo_count(topo[i]); c++) {
+                    const uint32_t ch = topo_first(topo[i]) + c;
+                    if (!(p.bits == 0 || topo_abs(topo[ch]))) frame_of[ch] = frame_of[i];
+                }
+            frame_bounds(frames[frame_of[i]], B.tri, B.order, nd.begin, nd.end, nd.lo, nd.hi);
+        }
+    }
+    auto put_frame = [&](float *w, uint32_t i) {
+        const Frame &f = frames[frame_of[i]];
+        w[6] = 0.0f;
+        w[kObbEps] = f.eps;
+        for (int k = 0; k < 3; k++) w[kObbOrigin + k] = f.o[k];
+        for (int a = 0; a < 3; a++)
+            for (int k = 0; k < 3; k++) w[kObbAxes + 3 * a + k] = f.a[a][k];
+    };
+
     // ---- encode, top-down (parents precede children in node order) ----
     std::vector<uint8_t> codes((size_t)n_nodes * stride, 0);
-    std::vector<float> absb((size_t)n_abs * 2 * K);
+    const uint32_t AW = abs_words(K, p.bv);
+    std::vector<float> absb((size_t)n_abs * AW);
     std::vector<float> dec((size_t)n_nodes * 2 * K);
     std::vector<uint32_t> parent(n_nodes, 0xFFFFFFFFu);
     for (uint32_t i = 0; i < n_nodes; i++)
@@ -399,12 +584,15 @@ std::string build_model(const float *V, uint32_t nv, const uint32_t *T, uint32_t
                 d[2 * k] = round_down(nd.lo[k]);
                 d[2 * k + 1] = round_up(nd.hi[k]);
             }
+            float wds[kObbWords];
+            memcpy(wds, d, 8 * (size_t)Kc);
+            if (obb) put_frame(wds, i);
             if (p.bits == 0) {
-                memcpy(code, d, 8 * (size_t)Kc);
+                memcpy(code, wds, 4 * (size_t)AW);
             } else {
                 uint32_t ai = abs_index[i];
                 memcpy(code, &ai, 4);
-                memcpy(&absb[(size_t)ai * 2 * Kc], d, 8 * (size_t)Kc);
+                memcpy(&absb[(size_t)ai * AW], wds, 4 * (size_t)AW);
             }
             continue;
         }
@@ -478,16 +666,18 @@ std::string validate_blob(const uint8_t *blob, size_t n, BlobHeader *hp, uint32_
     BlobHeader h;
     memcpy(&h, blob, sizeof h);
     if (h.magic != kMagic || h.version != kVersion) return "bad magic or version";
-    if (!((h.bv == 0 && h.K == 3) || (h.bv == 1 && h.K == 9))) return "bad BV type";
+    if (!((h.bv == kBvAabb && h.K == 3) || (h.bv == kBvDop18 && h.K == 9) || (h.bv == kBvObb && h.K == 3)))
+        return "bad BV type";
     if (!(h.bits == 0 || bits_are_codes(h.bits) || h.bits == kBitsFp16)) return "bad code width";
+    if (h.bv == kBvObb && h.bits == kBitsFp16) return "OBB models take bits 0, 8 or 16";
     if (!(h.branching == 2 || h.branching == 4 || h.branching == 8)) return "bad branching factor";
     if (h.leaf_size < 1 || h.leaf_size > kMaxLeaf) return "bad leaf size";
-    if (h.code_stride != code_stride_for(h.K, h.bits)) return "bad code stride";
+    if (h.code_stride != code_stride_for(h.K, h.bits, h.bv)) return "bad code stride";
     if (h.n_nodes < 1 || h.n_nodes > kIndexMask || h.n_tris < 1 || h.n_tris > kIndexMask) return "bad counts";
     if (h.total != n) return "size mismatch";
     auto fits = [&](uint64_t off, uint64_t bytes) { return off >= kHeaderBytes && off <= n && bytes <= n - off; };
     if (!fits(h.off_topo, 4ull * h.n_nodes) || !fits(h.off_codes, (uint64_t)h.code_stride * h.n_nodes) ||
-        !fits(h.off_abs, 8ull * h.K * h.n_abs) || !fits(h.off_tris, 36ull * h.n_tris) ||
+        !fits(h.off_abs, 4ull * abs_words(h.K, h.bv) * h.n_abs) || !fits(h.off_tris, 36ull * h.n_tris) ||
         !fits(h.off_perm, 4ull * h.n_tris) || !fits(h.off_treelets, 4ull * ((uint64_t)h.n_treelets + 1)))
         return "section out of range";
     if (h.off_topo % 4 || h.off_codes % 4 || h.off_abs % 4 || h.off_tris % 4 || h.off_perm % 4) return "misaligned section";

@@ -66,6 +66,7 @@ cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
     d.stride = h.code_stride;
     d.bits = h.bits;
     d.K = h.K;
+    d.bv = h.bv;
     d.leaf_size = h.leaf_size;
     d.depth = h.depth;
     d.branching = h.branching;
@@ -73,9 +74,9 @@ cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
     return d;
 }
 
-cbvh::StackLimits current_limits(uint32_t K, int mode)
+cbvh::StackLimits current_limits(uint32_t bv, int mode)
 {
-    cbvh::StackLimits l = cbvh::default_limits(K, mode);
+    cbvh::StackLimits l = cbvh::default_limits(bv, mode);
     uint32_t e = g_limit_entries.load(), r = g_limit_records.load();
     if (e) l.entries = e;
     if (r) l.records = r;
@@ -88,7 +89,7 @@ struct WsPlan {
     uint32_t item_cap, item_words, fix_cap;
 };
 
-WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap, uint64_t item_cap_max = 1ull << 24)
+WsPlan plan_workspace(uint32_t bv, int mode, uint32_t n, uint32_t pair_cap, uint64_t item_cap_max = 1ull << 24)
 {
     WsPlan p;
     uint64_t o = 0;
@@ -97,7 +98,7 @@ WsPlan plan_workspace(uint32_t K, int mode, uint32_t n, uint32_t pair_cap, uint6
         o = align_up(o + bytes, 256);
         return r;
     };
-    p.item_words = cbvh::item_words(K);
+    p.item_words = cbvh::item_words(bv);
     // donated work items (slots are not reused within a query): four per
     // pose plus slack; a donation that finds the queue full is not made
     uint64_t cap = 4ull * n + 262144ull;
@@ -166,7 +167,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     if (n > (1u << 30)) return fail(CBVH_E_INVALID, "too many poses");
     if (!ws) return fail(CBVH_E_INVALID, "workspace is NULL");
     if (!aligned(ws, 256)) return fail(CBVH_E_INVALID, "workspace not 256-byte aligned");
-    WsPlan plan = plan_workspace(a->hdr.K, mode, n, pair_cap, item_cap_max);
+    WsPlan plan = plan_workspace(a->hdr.bv, mode, n, pair_cap, item_cap_max);
     if (ws_bytes < plan.total) return fail(CBVH_E_CAPACITY, "workspace too small");
     uint8_t *w = (uint8_t *)ws;
     cbvh::QueryArgs q;
@@ -210,7 +211,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.ws.pair_cnt = (uint32_t *)(w + plan.pair_cnt);
     q.ws.pair_cursor = (uint32_t *)(w + plan.pair_cursor);
     q.ws.pair_keys = (unsigned long long *)(w + plan.pair_keys);
-    cbvh::StackLimits lim = current_limits(a->hdr.K, mode);
+    cbvh::StackLimits lim = current_limits(a->hdr.bv, mode);
     hipError_t e = cbvh::launch_query(q, lim, (hipStream_t)stream, pairs, pair_offsets);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return CBVH_OK;
@@ -230,7 +231,10 @@ cbvh_status cbvh_build(const float *V, uint32_t nv, const uint32_t *T, uint32_t 
         if (params->size != sizeof(cbvh_build_params)) return fail(CBVH_E_INVALID, "params.size mismatch");
         if (nt == 0 || nt > cbvh::kIndexMask) return fail(CBVH_E_INVALID, "triangle count out of range");
         if (nv == 0) return fail(CBVH_E_INVALID, "no vertices");
-        if (params->bv != CBVH_AABB && params->bv != CBVH_DOP18) return fail(CBVH_E_INVALID, "bad bv");
+        if (params->bv != CBVH_AABB && params->bv != CBVH_DOP18 && params->bv != CBVH_OBB)
+            return fail(CBVH_E_INVALID, "bad bv");
+        if (params->bv == CBVH_OBB && params->bits == CBVH_BITS_FP16)
+            return fail(CBVH_E_INVALID, "OBB models take bits 0, 8 or 16");
         if (!(params->branching == 2 || params->branching == 4 || params->branching == 8))
             return fail(CBVH_E_INVALID, "branching must be 2, 4 or 8");
         if (params->leaf_size < 1 || params->leaf_size > cbvh::kMaxLeaf) return fail(CBVH_E_INVALID, "leaf_size must be 1..8");
@@ -330,8 +334,8 @@ size_t cbvh_workspace_bytes(const cbvh_model *a, const cbvh_model *b, uint32_t n
 {
     if (!a || !b) return 0;
     int mode = (flags & CBVH_PAIRS) ? cbvh::MODE_PAIRS : cbvh::MODE_BOOL;
-    size_t x = plan_workspace(a->hdr.K, mode, n_poses, pair_capacity).total;
-    size_t y = plan_workspace(a->hdr.K, cbvh::MODE_DIST, n_poses, 0).total;
+    size_t x = plan_workspace(a->hdr.bv, mode, n_poses, pair_capacity).total;
+    size_t y = plan_workspace(a->hdr.bv, cbvh::MODE_DIST, n_poses, 0).total;
     return x > y ? x : y;
 }
 
@@ -369,8 +373,8 @@ cbvh_status cbvh_collide_static(const cbvh_model *a, const void *a_dev, const cb
     if (n == 0) return check_pair(a, a_dev, b, b_dev);
     // the item queue takes whatever the fixed array leaves after the rest of
     // the workspace (the donation path refuses items beyond it)
-    const WsPlan fixed = plan_workspace(a->hdr.K, cbvh::MODE_BOOL, n, 0, 0);
-    const uint64_t per_item = 4ull * cbvh::item_words(a->hdr.K) + 4ull, slack = 1024;
+    const WsPlan fixed = plan_workspace(a->hdr.bv, cbvh::MODE_BOOL, n, 0, 0);
+    const uint64_t per_item = 4ull * cbvh::item_words(a->hdr.bv) + 4ull, slack = 1024;
     if (fixed.total + slack + per_item * kStaticMinItems > cbvh::kStaticWorkspaceBytes)
         return fail(CBVH_E_CAPACITY, "the fixed workspace of cbvh_collide_static is too small for this batch");
     const uint64_t cap = (cbvh::kStaticWorkspaceBytes - fixed.total - slack) / per_item;

@@ -275,4 +275,141 @@ CBVH_GEOM_INLINE float dist_err_abs(const float *pose, float maxA, float maxB)
     return 256.0f * 0x1p-24f * (tnorm + 3.5f * (maxA + maxB));
 }
 
+// ---------------------------------------------------------------------------
+// Oriented boxes (OBB models)
+// ---------------------------------------------------------------------------
+// A node's descriptor d (20 floats): (lo, hi) of its three frame
+// coordinates, a word the traversal uses for the topology, eps, the frame's
+// origin o and axes a0, a1, a2.  The box is {o + u0 a0 + u1 a1 + u2 a2 : u in
+// the intervals}, i.e. {x_c + sum_j s_j r_j a_j : |s_j| <= 1} with centre
+// x_c = o + sum_j m_j a_j, m_j and r_j the intervals' midpoints and
+// half-lengths.
+
+// Allowances of the OBB test for a pose [R | t] whose columns' Gram matrix is
+// within rot_eps of the identity (so |R| <= rho = 1 + 1.5 rot_eps) and models
+// whose coordinates are at most maxA and maxB in magnitude:
+//   al[0] e_obb:  rounding of the centres and of D along B's unit-ish axes.
+//     Every centre coordinate and frame coordinate is below about 12 max in
+//     magnitude; placing A's centre, forming d = c - c_B and one dot product
+//     err by a few hundred u (rho maxA + |t| + maxB); 2^-14 covers it twice;
+//   al[1] e_obbA: the same along A's placed axes (length up to rho);
+//   al[2] delta_C: rounding of C_kj = b_k . g_j and of the placed axes g_j,
+//     per unit of extent (about 10 u rho |R|; 2^-18 rho max(1, rho));
+//   al[3] eta_R = 3.1 rot_eps: (R a_i).(R a_j) - a_i.a_j is at most
+//     |R^T R - I| |a_i| |a_j| <= 3 rot_eps (1 + eps)^2.
+CBVH_GEOM_INLINE void obb_allowances(const float *pose, float rot_eps, float maxA, float maxB, float *al)
+{
+    const float rho = 1.0f + 1.5f * rot_eps;
+    const float e = 0x1p-14f * (rho * maxA + maxB + fabsf(pose[3]) + fabsf(pose[7]) + fabsf(pose[11]));
+    al[0] = e;
+    al[1] = e * rho * 1.0625f;
+    al[2] = 0x1p-18f * rho * fmaxf(1.0f, rho);
+    al[3] = 3.1f * rot_eps;
+}
+
+// A's box placed by the pose, in generator form:
+//   out[0..2] centre c = R x_c + t, out[3] = r0 + r1 + r2;
+//   out[4 + 4j .. 6 + 4j] g_j = R a_j, out[7 + 4j] = r_j   (j = 0, 1, 2);
+//   out[16] eta = eps + eta_R, a bound on |(R a_i).(R a_j) - [i == j]|;
+//   out[17] radius of the placed box's circumscribed sphere (the Gram matrix
+//     of the placed axes has its largest eigenvalue below 1 + 3 eta);
+//   out[18], out[19] = 0.
+CBVH_GEOM_INLINE void obb_place(const Pose &P, const float *d, float eta_R, float *out)
+{
+    const float m0 = 0.5f * (d[0] + d[1]), m1 = 0.5f * (d[2] + d[3]), m2 = 0.5f * (d[4] + d[5]);
+    const float r0 = 0.5f * (d[1] - d[0]), r1 = 0.5f * (d[3] - d[2]), r2 = 0.5f * (d[5] - d[4]);
+    const float *o = d + 8, *a = d + 11;
+    V3<float> xc;
+    xc.x = __builtin_fmaf(m2, a[6], __builtin_fmaf(m1, a[3], __builtin_fmaf(m0, a[0], o[0])));
+    xc.y = __builtin_fmaf(m2, a[7], __builtin_fmaf(m1, a[4], __builtin_fmaf(m0, a[1], o[1])));
+    xc.z = __builtin_fmaf(m2, a[8], __builtin_fmaf(m1, a[5], __builtin_fmaf(m0, a[2], o[2])));
+    const V3<float> c = xform_f32(P, xc);
+    out[0] = c.x, out[1] = c.y, out[2] = c.z, out[3] = r0 + r1 + r2;
+    const float r[3] = {r0, r1, r2};
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const float ax = a[3 * j], ay = a[3 * j + 1], az = a[3 * j + 2];
+        out[4 + 4 * j] = __builtin_fmaf(P.R[0], ax, __builtin_fmaf(P.R[1], ay, P.R[2] * az));
+        out[5 + 4 * j] = __builtin_fmaf(P.R[3], ax, __builtin_fmaf(P.R[4], ay, P.R[5] * az));
+        out[6 + 4 * j] = __builtin_fmaf(P.R[6], ax, __builtin_fmaf(P.R[7], ay, P.R[8] * az));
+        out[7 + 4 * j] = r[j];
+    }
+    const float eta = d[7] + eta_R;
+    out[16] = eta;
+    out[17] = sqrtf(__builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, r2 * r2))) * (1.0f + 0x1p-20f + 2.0f * eta);
+    out[18] = 0.0f;
+    out[19] = 0.0f;
+}
+
+// A's placed box pa (from obb_place) against B's box (descriptor bB).  Along
+// any direction n the two are disjoint if
+//   |n.(c - c_B)| > sum_j r_j |n.g_j| + sum_k rb_k |n.b_k|.
+// The six face axes n = b_k and n = g_j give, with C_kj = |b_k . g_j|,
+// D_k = b_k . d, D'_j = g_j . d and d = c - c_B,
+//   gap_k  = |D_k|  - rb_k - sum_j C_kj r_j,
+//   gap'_j = |D'_j| - r_j  - sum_k C_kj rb_k,
+// where rb_k and r_j stand for each box's support along its own axes, exact
+// for orthonormal axes.  Allowances: eps_B sum(rb) and eta sum(r) for axes
+// that are not orthonormal, delta_C per unit of extent for the rounding of C
+// and of the placed axes, e_obb and e_obbA for the rounding of the centres
+// and of D, and 2^-20 of the large terms for the rounding of the sums.  The
+// nine edge-edge axes of the full separating-axis test are left out: a
+// subset of the axes never separates boxes that overlap, so the test stays
+// conservative.  *sep > 0 proves the boxes disjoint.  With DIST, *lb is a
+// lower bound on their distance: each gap times a lower bound on 1 / |n|
+// (|b_k| <= 1 + eps_B, |g_j| <= 1 + eta + delta_C), and the gap of the
+// circumscribed spheres; negative where the boxes may overlap.
+template <bool DIST>
+CBVH_GEOM_INLINE void obb_gap(const float *pa, const float *bB, const float *al, float *sep_out, float *lb_out)
+{
+    const float e_obb = al[0], e_obbA = al[1], dC = al[2];
+    const float *o = bB + 8, *bk = bB + 11;
+    const float epsB = bB[7], etaA = pa[16];
+    float mb[3], rb[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        mb[k] = 0.5f * (bB[2 * k] + bB[2 * k + 1]);
+        rb[k] = 0.5f * (bB[2 * k + 1] - bB[2 * k]);
+    }
+    const float rsumB = rb[0] + rb[1] + rb[2], rsumA = pa[3];
+    const float dx = pa[0] - __builtin_fmaf(mb[2], bk[6], __builtin_fmaf(mb[1], bk[3], __builtin_fmaf(mb[0], bk[0], o[0])));
+    const float dy = pa[1] - __builtin_fmaf(mb[2], bk[7], __builtin_fmaf(mb[1], bk[4], __builtin_fmaf(mb[0], bk[1], o[1])));
+    const float dz = pa[2] - __builtin_fmaf(mb[2], bk[8], __builtin_fmaf(mb[1], bk[5], __builtin_fmaf(mb[0], bk[2], o[2])));
+    float C[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            C[k][j] = fabsf(__builtin_fmaf(bk[3 * k], pa[4 + 4 * j],
+                                           __builtin_fmaf(bk[3 * k + 1], pa[5 + 4 * j], bk[3 * k + 2] * pa[6 + 4 * j])));
+    const float allowB = __builtin_fmaf(epsB, rsumB, __builtin_fmaf(dC, rsumA, e_obb));
+    const float allowA = __builtin_fmaf(etaA + dC, rsumA, __builtin_fmaf(dC, rsumB, e_obbA));
+    float sep = -INFINITY, lb = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const float D = __builtin_fmaf(bk[3 * k], dx, __builtin_fmaf(bk[3 * k + 1], dy, bk[3 * k + 2] * dz));
+        const float S = __builtin_fmaf(C[k][0], pa[7], __builtin_fmaf(C[k][1], pa[11], __builtin_fmaf(C[k][2], pa[15], rb[k])));
+        const float g = __builtin_fmaf(fabsf(D), 1.0f - 0x1p-20f, -S * (1.0f + 0x1p-20f)) - allowB;
+        sep = fmaxf(sep, g);
+        if (DIST) lb = fmaxf(lb, g * (1.0f - epsB - 0x1p-20f));
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const float D = __builtin_fmaf(pa[4 + 4 * j], dx, __builtin_fmaf(pa[5 + 4 * j], dy, pa[6 + 4 * j] * dz));
+        const float S = __builtin_fmaf(C[0][j], rb[0], __builtin_fmaf(C[1][j], rb[1], __builtin_fmaf(C[2][j], rb[2], pa[7 + 4 * j])));
+        const float g = __builtin_fmaf(fabsf(D), 1.0f - 0x1p-20f, -S * (1.0f + 0x1p-20f)) - allowA;
+        sep = fmaxf(sep, g);
+        if (DIST) lb = fmaxf(lb, g * (1.0f - etaA - dC - 0x1p-20f));
+    }
+    if (DIST) {
+        const float radB = sqrtf(__builtin_fmaf(rb[0], rb[0], __builtin_fmaf(rb[1], rb[1], rb[2] * rb[2]))) *
+                           (1.0f + 0x1p-20f + 2.0f * epsB);
+        const float gs = sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * (1.0f - 0x1p-20f) - pa[17] -
+                         radB - 2.0f * e_obb;
+        lb = fmaxf(lb, gs);
+    }
+    *sep_out = sep;
+    *lb_out = lb;
+}
+
 }  // namespace cbvh

@@ -20,6 +20,7 @@ struct DevModel {
     const uint32_t *perm;
     const uint32_t *treelets;
     uint32_t n_nodes, n_tris, n_treelets, stride, bits, K, leaf_size, depth, branching;
+    uint32_t bv;  // kBvAabb, kBvDop18 or kBvObb
     float max_abs;
 };
 
@@ -120,10 +121,10 @@ struct QueryArgs {
     Workspace ws;
 };
 
-// Bytes of one wave's traversal state for K slabs, a mode and limits.
-size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim, uint32_t bits);
-StackLimits default_limits(uint32_t K, int mode);
-uint32_t item_words(uint32_t K);
+// Bytes of one wave's traversal state for a BV type, a mode and limits.
+size_t wave_state_bytes(uint32_t bv, int mode, const StackLimits &lim);
+StackLimits default_limits(uint32_t bv, int mode);
+uint32_t item_words(uint32_t bv);
 
 // Enqueue the whole query on `stream`: init, the traversal, and the finalize
 // (distances, or count / scan / scatter / sort of pair lists).

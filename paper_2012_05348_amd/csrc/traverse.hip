@@ -116,7 +116,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t)
 // ---------------------------------------------------------------------------
 // A record is one decoded BV: 2K bounds (lo, hi per slab), its topology word
 // and one pad word, 16-byte aligned so that it moves in 16-byte LDS accesses.
-__host__ __device__ constexpr uint32_t rec_words(uint32_t K) { return 2 * K + 2; }
+// An OBB record is its node's whole descriptor (frame included), with the
+// topology word in the descriptor's word 6.
+__host__ __device__ constexpr uint32_t rec_words(uint32_t K, bool obb = false) { return obb ? kObbWords : 2 * K + 2; }
+// words a decode produces per node: the bounds, or an OBB's whole descriptor
+__host__ __device__ constexpr uint32_t dec_words(uint32_t K, bool obb) { return obb ? kObbWords : 2 * K; }
 // Collision queries keep both topology words in each pending entry (one LDS
 // access pops an entry); distance queries, whose stacks are far deeper, read
 // them from the records.
@@ -126,7 +130,7 @@ struct Layout {
     uint32_t ctr, pz, xf, rec, ta, ta_topo, tsph, ent, ent_tp, ent_lb, lq, lq_lb, lscan, total;
 };
 
-__host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim, uint32_t bits)
+__host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits lim, bool obb)
 {
     Layout L;
     uint32_t o = 0;
@@ -136,12 +140,15 @@ __host__ __device__ inline Layout make_layout(uint32_t K, int mode, StackLimits 
         return r;
     };
     L.ctr = take(8 * C_NUM);
-    L.pz = take(64);
+    L.pz = take(80);
     L.xf = take(32 * K);
-    L.rec = take(4 * rec_words(K) * lim.records);
-    L.ta = (mode == MODE_DIST && K == 3) ? o : take(4 * rec_words(K) * TA_MAX);  // AABB distance tests read no transform
+    L.rec = take(4 * rec_words(K, obb) * lim.records);
+    // AABB distance tests and OBB tests read no support-function transform
+    L.ta = ((mode == MODE_DIST && K == 3) || obb) ? o : take(4 * rec_words(K) * TA_MAX);
     L.ta_topo = take(4 * TA_MAX);
-    L.tsph = (mode == MODE_DIST || K == 3) ? take(32 * TA_MAX) : o;
+    // A's records placed by the pose: sphere and half extents (2 float4), or
+    // the placed OBB (5 float4)
+    L.tsph = obb ? take(80 * TA_MAX) : (mode == MODE_DIST || K == 3) ? take(32 * TA_MAX) : o;
     L.ent = take(4 * lim.entries);
     L.ent_tp = topo_in_entry(mode) ? take(8 * lim.entries) : o;
     L.ent_lb = mode == MODE_DIST ? take(4 * lim.entries) : o;
@@ -256,19 +263,19 @@ __device__ __forceinline__ T gload(const void *p)
 // K 8-bit code pairs (one 16-bit load each), K binary16 pairs, or 2K FP32
 // bounds.  All of them are read up front, before the topology word is
 // known, so that a node costs one memory round trip.
-template <int K, int BITS>
+template <int K, int BITS, bool OBB = false>
 struct NodeWords {
-    static constexpr int N = BITS == 0 ? 2 * K : K;
+    static constexpr int N = BITS == 0 ? (int)dec_words(K, OBB) : K;
     uint32_t w[N];
 };
 
-template <int K, int BITS>
-__device__ __forceinline__ void load_node(const DevModel &M, uint32_t node, uint32_t &topo, NodeWords<K, BITS> &nw)
+template <int K, int BITS, bool OBB = false>
+__device__ __forceinline__ void load_node(const DevModel &M, uint32_t node, uint32_t &topo, NodeWords<K, BITS, OBB> &nw)
 {
     topo = gload<uint32_t>(M.topo + node);
     const uint8_t *code = M.codes + (size_t)node * M.stride;
 #pragma unroll
-    for (int k = 0; k < NodeWords<K, BITS>::N; k++)
+    for (int k = 0; k < NodeWords<K, BITS, OBB>::N; k++)
         nw.w[k] = BITS == 8 ? (uint32_t)gload<uint16_t>(code + 2 * k) : gload<uint32_t>(code + 4 * k);
 }
 
@@ -276,8 +283,10 @@ __device__ __forceinline__ void load_node(const DevModel &M, uint32_t node, uint
 // bounds: E = Ph - Pl, s = E * 2^-BITS (0 if E < 2^-100), lo = fma(ql, s, Pl),
 // hi = fma(-qh, s, Ph).  Absolute nodes (treelet tops) and uncompressed
 // models read FP32 bounds instead, half-precision models binary16 bounds.
-template <int K, int BITS>
-__device__ __forceinline__ void decode_rel(const NodeWords<K, BITS> &nw, const float *parent, float out[2 * K])
+// An OBB node decoded from codes keeps its parent's frame (words 2K on).
+template <int K, int BITS, bool OBB = false>
+__device__ __forceinline__ void decode_rel(const NodeWords<K, BITS, OBB> &nw, const float *parent,
+                                           float out[dec_words(K, OBB)])
 {
     if constexpr (BITS == (int)kBitsFp16) {
         // binary16 absolute bounds, widened exactly
@@ -288,8 +297,12 @@ __device__ __forceinline__ void decode_rel(const NodeWords<K, BITS> &nw, const f
         }
     } else if constexpr (BITS == 0) {
 #pragma unroll
-        for (int k = 0; k < 2 * K; k++) out[k] = __uint_as_float(nw.w[k]);
+        for (int k = 0; k < (int)dec_words(K, OBB); k++) out[k] = __uint_as_float(nw.w[k]);
     } else {
+        if constexpr (OBB) {
+#pragma unroll
+            for (int k = 2 * K; k < (int)kObbWords; k++) out[k] = parent[k];
+        }
         const float scale = 1.0f / (float)(1u << (BITS & 31));
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -307,46 +320,49 @@ __device__ __forceinline__ void decode_rel(const NodeWords<K, BITS> &nw, const f
 
 // an absolute node of a coded model: the first four code bytes hold its
 // index in the FP32 table
-template <int K, int BITS>
-__device__ __forceinline__ void decode_abs(const DevModel &M, const NodeWords<K, BITS> &nw, float out[2 * K])
+template <int K, int BITS, bool OBB = false>
+__device__ __forceinline__ void decode_abs(const DevModel &M, const NodeWords<K, BITS, OBB> &nw,
+                                           float out[dec_words(K, OBB)])
 {
+    constexpr uint32_t DW = dec_words(K, OBB);
     const uint32_t ai = BITS == 8 ? (nw.w[0] | (nw.w[1] << 16)) : nw.w[0];
-    const uint64_t *c = (const uint64_t *)(M.absb + (size_t)ai * 2 * K);
+    const uint64_t *c = (const uint64_t *)(M.absb + (size_t)ai * DW);
 #pragma unroll
-    for (int k = 0; k < K; k++) {
+    for (int k = 0; k < (int)DW / 2; k++) {
         const uint64_t w = gload<uint64_t>(c + k);
         out[2 * k] = __uint_as_float((uint32_t)w);
         out[2 * k + 1] = __uint_as_float((uint32_t)(w >> 32));
     }
 }
 
-template <int K, int BITS, typename ParentPtr>
-__device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
-                                             ParentPtr parent, float out[2 * K])
+template <int K, int BITS, bool OBB = false, typename ParentPtr>
+__device__ __forceinline__ void decode_words(const DevModel &M, uint32_t topo, const NodeWords<K, BITS, OBB> &nw,
+                                             ParentPtr parent, float out[dec_words(K, OBB)])
 {
-    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS>(M, nw, out);
-    else decode_rel<K, BITS>(nw, parent, out);
+    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS, OBB>(M, nw, out);
+    else decode_rel<K, BITS, OBB>(nw, parent, out);
 }
 
 // The traversal's decode of a child whose parent bounds are at hand: the
 // relative decode always runs (so the code words are consumed before any
 // branch and their loads travel together with the topology word's), and
 // the rare treelet tops then read their absolute bounds.
-template <int K, int BITS>
-__device__ __forceinline__ void decode_child(const DevModel &M, uint32_t topo, const NodeWords<K, BITS> &nw,
-                                             const float *parent, float out[2 * K])
+template <int K, int BITS, bool OBB = false>
+__device__ __forceinline__ void decode_child(const DevModel &M, uint32_t topo, const NodeWords<K, BITS, OBB> &nw,
+                                             const float *parent, float out[dec_words(K, OBB)])
 {
-    decode_rel<K, BITS>(nw, parent, out);
-    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS>(M, nw, out);
+    decode_rel<K, BITS, OBB>(nw, parent, out);
+    if (bits_are_codes((uint32_t)BITS) && topo_abs(topo)) decode_abs<K, BITS, OBB>(M, nw, out);
 }
 
-template <int K, int BITS, typename ParentPtr>
-__device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, ParentPtr parent, float out[2 * K])
+template <int K, int BITS, bool OBB = false, typename ParentPtr>
+__device__ __forceinline__ void decode_node(const DevModel &M, uint32_t node, ParentPtr parent,
+                                            float out[dec_words(K, OBB)])
 {
-    NodeWords<K, BITS> nw;
+    NodeWords<K, BITS, OBB> nw;
     uint32_t topo;
-    load_node<K, BITS>(M, node, topo, nw);
-    decode_words<K, BITS>(M, topo, nw, parent, out);
+    load_node<K, BITS, OBB>(M, node, topo, nw);
+    decode_words<K, BITS, OBB>(M, topo, nw, parent, out);
 }
 
 __device__ __forceinline__ void load_tri(const float *tris, uint32_t i, V3<float> t[3])
@@ -414,7 +430,8 @@ __device__ __forceinline__ uint32_t meta_word(uint32_t aoff, uint32_t boff, uint
 // A donated work item: a node pair that passed its BV test, with both
 // nodes' decoded bounds so that it is self-contained, or a leaf pair.
 //   u32 pose, u32 topo A, u32 topo B, f32 lower bound, f32 A[2K], f32 B[2K]
-__host__ __device__ constexpr uint32_t words_of_item(uint32_t K) { return 4u + 4u * K; }
+// (OBB models: each node's whole decoded descriptor, 20 words)
+__host__ __device__ constexpr uint32_t words_of_item(uint32_t K, bool obb = false) { return 4u + 2u * dec_words(K, obb); }
 
 // Queue accesses between waves on different XCDs go through read-modify-write
 // atomics at device scope: they are performed at the device's coherence
@@ -483,28 +500,33 @@ constexpr uint32_t kVoidItem = 0xFFFFFFFFu;
 // are merged in device memory, so results do not depend on the split.
 // ---------------------------------------------------------------------------
 // Collision modes and distance queries of AABB models fit 3 waves per SIMD
-// (168 VGPRs); distance queries of 18-DOP models need more.
-template <int K, int BITS, int MODE>
+// (168 VGPRs); distance queries of 18-DOP or OBB models need more.  OBB
+// selects oriented boxes (K == 3 slabs in per-node frames).
+template <int K, int BITS, int MODE, bool OBB>
 __global__ __launch_bounds__(kMaxWavesPerGroup * WAVE)
-__attribute__((amdgpu_waves_per_eu((MODE == MODE_DIST && K == 9) ? 2 : 3)))
+__attribute__((amdgpu_waves_per_eu((MODE == MODE_DIST && (K == 9 || OBB)) ? 2 : 3)))
 void traverse_kernel(QueryArgs q, StackLimits lim)
 {
+    static_assert(!OBB || (K == 3 && BITS != (int)kBitsFp16), "OBB models: 3 slabs, bits 0, 8 or 16");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t lane = __lane_id();
-    const Layout LY = make_layout(K, MODE, lim, (uint32_t)BITS);
+    const Layout LY = make_layout(K, MODE, lim, OBB);
     // a workgroup holds one or more independent waves (the launch's
     // workgroup shape); each has its own slice of LDS
     const uint32_t wave_in_group = uni(threadIdx.x / WAVE), waves_per_group = blockDim.x / WAVE;
     const uint32_t wave_id = blockIdx.x * waves_per_group + wave_in_group;
     const uint32_t n_waves = gridDim.x * waves_per_group;
     unsigned char *base = lds_raw + (size_t)wave_in_group * LY.total;
-    constexpr uint32_t RW = rec_words(K);  // floats per record (and per transformed A record)
-    constexpr uint32_t RV = RW / 4;        // float4 per record
+    constexpr uint32_t RW = rec_words(K, OBB);  // floats per record
+    constexpr uint32_t RV = RW / 4;             // float4 per record
+    constexpr uint32_t DW = dec_words(K, OBB);  // decoded words per node
+    constexpr uint32_t TW = rec_words(K);       // floats per transformed A record
     constexpr bool kTopoEnt = topo_in_entry(MODE);
     float4 *xf = (float4 *)(base + LY.xf);
     // the current pose and its error allowances, kept in LDS (read where
     // needed, so that they hold no scalar registers across the traversal):
-    // rows (R_i0, R_i1, R_i2, t_i), then (e_abs, e_sph, e_dir, rot_eps)
+    // rows (R_i0, R_i1, R_i2, t_i), then (e_abs, e_sph, e_dir, rot_eps), then
+    // the OBB test's allowances (e_obb, e_obbA, delta_C, eta_R)
     float4 *pz = (float4 *)(base + LY.pz);
     auto pose_of = [&]() -> Pose {
         Pose P;
@@ -527,7 +549,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     uint32_t *lscan = (uint32_t *)(base + LY.lscan);  // leaf step: prefix sums of the taken leaf pairs
     auto rec_topo_ref = [&](uint32_t r) -> uint32_t & { return ((uint32_t *)rec)[(size_t)r * RW + 2 * K]; };
 
-    constexpr uint32_t IW = words_of_item(K);       // dwords per item
+    constexpr uint32_t IW = words_of_item(K, OBB);  // dwords per item
     constexpr uint32_t CPL = (uint32_t)WAVE / (uint32_t)K;  // records per transform pass
     constexpr uint32_t IPI = (uint32_t)WAVE / IW;   // items written per wave instruction
     const DevModel &MA = q.A;
@@ -593,8 +615,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         else if (w == 1) val = entry_topo(i, ee).x;
                         else if (w == 2) val = entry_topo(i, ee).y;
                         else if (w == 3) val = MODE == MODE_DIST ? __float_as_uint(ent_lb[i]) : 0u;
-                        else if (w < 4 + 2 * K) val = __float_as_uint(rec[(size_t)rA * RW + (w - 4)]);
-                        else val = __float_as_uint(rec[(size_t)rB * RW + (w - 4 - 2 * K)]);
+                        else if (w < 4 + DW) val = __float_as_uint(rec[(size_t)rA * RW + (w - 4)]);
+                        else val = __float_as_uint(rec[(size_t)rB * RW + (w - 4 - DW)]);
                     } else {
                         const uint32_t j = i - n_ent;
                         const uint2 le = lq[j];
@@ -622,7 +644,14 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     // and half extents in its own frame.
     auto prep_A = [&](uint32_t c, const float *b, uint32_t topo) {
         ta_topo[c] = topo;
-        if constexpr (MODE == MODE_DIST || K == 3) {
+        if constexpr (OBB) {
+            // the box placed by the pose, in generator form
+            float pl[20];
+            obb_place(pose_of(), b, pz[4].w, pl);
+            float4 *d = tsph + 5 * c;
+#pragma unroll
+            for (int v = 0; v < 5; v++) d[v] = make_float4(pl[4 * v], pl[4 * v + 1], pl[4 * v + 2], pl[4 * v + 3]);
+        } else if constexpr (MODE == MODE_DIST || K == 3) {
             const Pose P = pose_of();
             const float rot_eps = pz[3].w;
             V3<float> cc = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
@@ -637,9 +666,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
     auto store_rec = [&](uint32_t r, const float *b, uint32_t topo) {
         float t[RW];
 #pragma unroll
-        for (uint32_t k = 0; k < 2 * K; k++) t[k] = b[k];
+        for (uint32_t k = 0; k < DW; k++) t[k] = b[k];
         t[2 * K] = __uint_as_float(topo);
-        t[2 * K + 1] = 0.0f;
+        if constexpr (!OBB) t[2 * K + 1] = 0.0f;
         float4 *dst = (float4 *)(rec + (size_t)r * RW);
 #pragma unroll
         for (uint32_t v = 0; v < RV; v++) dst[v] = make_float4(t[4 * v], t[4 * v + 1], t[4 * v + 2], t[4 * v + 3]);
@@ -753,8 +782,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             it_tB = lane_of(v, 2);
             it_lb = __uint_as_float(lane_of(v, 3));
             // records 0 and 1 hold the item's two decoded BVs
-            if (lane >= 4 && lane < 4 + 2 * K) rec[lane - 4] = __uint_as_float(v);
-            if (lane >= 4 + 2 * K && lane < IW) rec[RW + (lane - 4 - 2 * K)] = __uint_as_float(v);
+            if (lane >= 4 && lane < 4 + DW) rec[lane - 4] = __uint_as_float(v);
+            if (lane >= 4 + DW && lane < IW) rec[RW + (lane - 4 - DW)] = __uint_as_float(v);
             from_item = true;
             if (MODE == MODE_BOOL) {
                 uint32_t decided = 0;
@@ -786,7 +815,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     for (int j = 0; j < 3; j++) P.R[3 * i + j] = q.poses[12 * (size_t)pose + 4 * i + j];
                     P.t[i] = q.poses[12 * (size_t)pose + 4 * i + 3];
                 }
-                pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, xf, lane);
+                if constexpr (!OBB) pose_setup<K>(&q.poses[12 * (size_t)pose], MA.max_abs, xf, lane);
                 // distance: FP32 leaf-distance error bound, and the absolute
                 // rounding allowance of the sphere bound
                 const float e_abs = dist_err_abs(&q.poses[12 * (size_t)pose], MA.max_abs, MB.max_abs);
@@ -817,6 +846,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
 #pragma unroll
                     for (int i = 0; i < 3; i++) pz[i] = make_float4(P.R[3 * i], P.R[3 * i + 1], P.R[3 * i + 2], P.t[i]);
                     pz[3] = make_float4(e_abs, e_sph, e_dir, rot_eps);
+                    if constexpr (OBB) {
+                        float al[4];
+                        obb_allowances(&q.poses[12 * (size_t)pose], rot_eps, MA.max_abs, MB.max_abs, al);
+                        pz[4] = make_float4(al[0], al[1], al[2], al[3]);
+                    }
                 }
             }
             wave_sync();
@@ -847,11 +881,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             // root frame: record 0 = A's root, record 1 = B's root; the root pair is tested first
             if (lane < 2) {
                 const DevModel &M = lane == 0 ? MA : MB;
-                NodeWords<K, BITS> nw;
+                NodeWords<K, BITS, OBB> nw;
                 uint32_t tw;
-                load_node<K, BITS>(M, 0, tw, nw);
-                float bnd[2 * K];
-                decode_words<K, BITS>(M, tw, nw, (const float *)nullptr, bnd);
+                load_node<K, BITS, OBB>(M, 0, tw, nw);
+                float bnd[DW];
+                decode_words<K, BITS, OBB>(M, tw, nw, (const float *)nullptr, bnd);
                 store_rec(lane, bnd, tw);
                 if (lane == 0) prep_A(0, bnd, tw);
             }
@@ -902,7 +936,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 // lane = (record c, slab my_k), CPL records per pass; each
                 // generator reads its slab's (lo, hi) pair at once (distance
                 // tests of AABB models read only the spheres prepared at decode)
-                if constexpr (MODE != MODE_DIST || K != 3) {
+                if constexpr ((MODE != MODE_DIST || K != 3) && !OBB) {
                     const uint32_t up = __float_as_uint(xf0.w);
                     const uint32_t a0 = (up & 0xFFu) >> 1, a1 = ((up >> 8) & 0xFFu) >> 1, a2 = ((up >> 16) & 0xFFu) >> 1;
                     const bool h0 = (up & 1u) != 0, h1 = (up & 0x100u) != 0, h2 = (up & 0x10000u) != 0;
@@ -917,7 +951,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                                            __builtin_fmaf(xf0.y, h1 ? p1.y : p1.x, __builtin_fmaf(xf0.x, h0 ? p0.y : p0.x, xfU)));
                             const float L = __builtin_fmaf(xf0.z, h2 ? p2.x : p2.y,
                                                            __builtin_fmaf(xf0.y, h1 ? p1.x : p1.y, __builtin_fmaf(xf0.x, h0 ? p0.x : p0.y, xfL)));
-                            *(float2 *)(ta + (size_t)ca * RW + 2 * my_k) = make_float2(L, U);
+                            *(float2 *)(ta + (size_t)ca * TW + 2 * my_k) = make_float2(L, U);
                         }
                     }
                     wave_sync();
@@ -952,7 +986,23 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     float bB[RW];
                     load_rec(recB, bB);
                     tB_w = __float_as_uint(bB[2 * K]);
-                    if constexpr (MODE == MODE_DIST) {
+                    if constexpr (OBB) {
+                        float pa[20], sep;
+#pragma unroll
+                        for (int v = 0; v < 5; v++) {
+                            const float4 x = tsph[5 * ia + v];
+                            pa[4 * v] = x.x, pa[4 * v + 1] = x.y, pa[4 * v + 2] = x.z, pa[4 * v + 3] = x.w;
+                        }
+                        const float4 a4 = pz[4];
+                        const float al[4] = {a4.x, a4.y, a4.z, a4.w};
+                        obb_gap<MODE == MODE_DIST>(pa, bB, al, &sep, &lb);
+                        if constexpr (MODE == MODE_DIST) {
+                            survive = lb <= tau;
+                        } else {
+                            lb = sep;
+                            survive = !(sep > 0.0f);
+                        }
+                    } else if constexpr (MODE == MODE_DIST) {
                         // A lower bound on the distance of the two BVs (the largest of
                         // the ones below); where the boxes overlap it is negative, and
                         // then its value orders the traversal: the most deeply
@@ -965,7 +1015,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         if constexpr (K != 3) {
                             float tA[RW];
                             {
-                                const float4 *src = (const float4 *)(ta + (size_t)ia * RW);
+                                const float4 *src = (const float4 *)(ta + (size_t)ia * TW);
 #pragma unroll
                                 for (uint32_t v = 0; v < RV; v++) {
                                     const float4 x = src[v];
@@ -1000,7 +1050,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         // slab) orders the traversal, the deepest overlap first
                         float tA[RW];
                         {
-                            const float4 *src = (const float4 *)(ta + (size_t)ia * RW);
+                            const float4 *src = (const float4 *)(ta + (size_t)ia * TW);
 #pragma unroll
                             for (uint32_t v = 0; v < RV; v++) {
                                 const float4 x = src[v];
@@ -1430,7 +1480,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 g_pB = gather(my_tB, e);
             }
             uint32_t my_topo = 0;
-            float my_b[2 * K];
+            float my_b[DW];
             const bool dec = lane < total_rec;
             {
                 // algorithmic bytes: topology word and codes of every decoded child
@@ -1450,13 +1500,13 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     load_rec(prec, pb);
                     my_topo = ptopo;
 #pragma unroll
-                    for (int k = 0; k < 2 * K; k++) my_b[k] = pb[k];
+                    for (int k = 0; k < (int)DW; k++) my_b[k] = pb[k];
                 } else {
                     const DevModel &M = sideA ? MA : MB;
-                    NodeWords<K, BITS> nw;
-                    load_node<K, BITS>(M, topo_first(ptopo) + c, my_topo, nw);
+                    NodeWords<K, BITS, OBB> nw;
+                    load_node<K, BITS, OBB>(M, topo_first(ptopo) + c, my_topo, nw);
                     load_rec(prec, pb);
-                    decode_child<K, BITS>(M, my_topo, nw, pb, my_b);
+                    decode_child<K, BITS, OBB>(M, my_topo, nw, pb, my_b);
                 }
             }
             wave_sync();
@@ -1718,16 +1768,18 @@ __global__ __launch_bounds__(256) void pair_sort_kernel(const uint32_t *offsets,
 // decode every node: one thread per treelet walks its nodes in order (the
 // top group is absolute, every other node's parent lies earlier in the
 // same treelet), the random access that treelets give
-template <int K, int BITS>
+template <int K, int BITS, bool OBB = false>
 __global__ void decode_all_kernel(DevModel M, float *out)
 {
+    // per node: its bounds (lo, hi per slab), or an OBB's whole descriptor
+    constexpr uint32_t DW = dec_words(K, OBB);
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (!bits_are_codes((uint32_t)BITS)) {
         // absolute descriptors (FP32 or FP16): one thread per node
         for (uint32_t i = t; i < M.n_nodes; i += gridDim.x * blockDim.x) {
-            float b[2 * K];
-            decode_node<K, BITS>(M, i, (const float *)nullptr, b);
-            for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
+            float b[DW];
+            decode_node<K, BITS, OBB>(M, i, (const float *)nullptr, b);
+            for (uint32_t k = 0; k < DW; k++) out[(size_t)i * DW + k] = b[k];
         }
         return;
     }
@@ -1736,18 +1788,18 @@ __global__ void decode_all_kernel(DevModel M, float *out)
     for (uint32_t i = first; i < end; i++) {
         uint32_t w = M.topo[i];
         if (topo_abs(w)) {
-            float b[2 * K];
-            decode_node<K, BITS>(M, i, (const float *)nullptr, b);
-            for (int k = 0; k < 2 * K; k++) out[(size_t)i * 2 * K + k] = b[k];
+            float b[DW];
+            decode_node<K, BITS, OBB>(M, i, (const float *)nullptr, b);
+            for (uint32_t k = 0; k < DW; k++) out[(size_t)i * DW + k] = b[k];
         }
         if (!topo_leaf(w)) {
             uint32_t c0 = topo_first(w), nc = topo_count(w);
             if (c0 >= end) continue;  // children start another treelet (absolute there)
             for (uint32_t c = 0; c < nc; c++) {
                 uint32_t node = c0 + c;
-                float b[2 * K];
-                decode_node<K, BITS>(M, node, out + (size_t)i * 2 * K, b);
-                for (int k = 0; k < 2 * K; k++) out[(size_t)node * 2 * K + k] = b[k];
+                float b[DW];
+                decode_node<K, BITS, OBB>(M, node, out + (size_t)i * DW, b);
+                for (uint32_t k = 0; k < DW; k++) out[(size_t)node * DW + k] = b[k];
             }
         }
     }
@@ -1777,10 +1829,10 @@ uint32_t env_u32(const char *name, uint32_t dflt)
     return x ? (uint32_t)x : dflt;
 }
 
-template <int K, int BITS, int MODE>
+template <int K, int BITS, int MODE, bool OBB>
 hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
-    Layout L = make_layout(K, MODE, lim, (uint32_t)BITS);
+    Layout L = make_layout(K, MODE, lim, OBB);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1791,7 +1843,7 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // workgroup shape: waves per workgroup (independent waves; 1, 2 or 4)
     uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", 1u);
     wpg = wpg >= 4 ? 4u : wpg >= 2 ? 2u : 1u;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE, OBB>),
                                                      WAVE * wpg, L.total * wpg) != hipSuccess || occ < 1) {
         (void)hipGetLastError();  // clear a failed query's error; fall back to the LDS bound
         occ = (int)(160u * 1024u / (L.total * wpg + 256u));
@@ -1836,17 +1888,17 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // collision queries: units past 16 steps get issue priority (about 2 % on
     // the scaled workload); distance queries gain nothing from it
     qq.prio_steps = env_u32("CBVH_PRIO_STEPS", MODE == MODE_DIST ? 0u : 16u);
-    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE>), dim3(grid), dim3(WAVE * wpg), L.total * wpg, s, qq, lim);
+    hipLaunchKernelGGL((traverse_kernel<K, BITS, MODE, OBB>), dim3(grid), dim3(WAVE * wpg), L.total * wpg, s, qq, lim);
     return hipGetLastError();
 }
 
-template <int K, int BITS>
+template <int K, int BITS, bool OBB = false>
 hipError_t launch_mode(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
     switch (q.mode) {
-    case MODE_BOOL: return launch_traverse<K, BITS, MODE_BOOL>(q, lim, s);
-    case MODE_PAIRS: return launch_traverse<K, BITS, MODE_PAIRS>(q, lim, s);
-    default: return launch_traverse<K, BITS, MODE_DIST>(q, lim, s);
+    case MODE_BOOL: return launch_traverse<K, BITS, MODE_BOOL, OBB>(q, lim, s);
+    case MODE_PAIRS: return launch_traverse<K, BITS, MODE_PAIRS, OBB>(q, lim, s);
+    default: return launch_traverse<K, BITS, MODE_DIST, OBB>(q, lim, s);
     }
 }
 
@@ -1854,6 +1906,12 @@ hipError_t launch_any(const QueryArgs &q, const StackLimits &lim, hipStream_t s)
 {
     uint32_t K = q.A.K, bits = q.A.bits;
     constexpr int F16 = (int)kBitsFp16;
+    if (q.A.bv == kBvObb) {
+        if (bits == 0) return launch_mode<3, 0, true>(q, lim, s);
+        if (bits == 8) return launch_mode<3, 8, true>(q, lim, s);
+        if (bits == 16) return launch_mode<3, 16, true>(q, lim, s);
+        return hipErrorInvalidValue;  // rejected by the builder and the loader
+    }
     if (K == 3) {
         if (bits == 0) return launch_mode<3, 0>(q, lim, s);
         if (bits == 8) return launch_mode<3, 8>(q, lim, s);
@@ -1893,22 +1951,24 @@ hipError_t static_workspace(void **out)
     return hipSuccess;
 }
 
-size_t wave_state_bytes(uint32_t K, int mode, const StackLimits &lim, uint32_t bits)
+size_t wave_state_bytes(uint32_t bv, int mode, const StackLimits &lim)
 {
-    return make_layout(K, mode, lim, bits).total;
+    return make_layout(bv_slabs(bv), mode, lim, bv == kBvObb).total;
 }
 
-StackLimits default_limits(uint32_t K, int mode)
+StackLimits default_limits(uint32_t bv, int mode)
 {
     // branch-and-bound keeps many more pairs pending than collision queries;
     // the sizes let 10 waves (AABB) or 8 waves (18-DOP, the most its
     // registers allow) fit a CU, about 5 % faster than 8 and 7 waves with
-    // the larger stacks used before (768 and 512 entries)
-    if (mode == MODE_DIST) return K == 9 ? StackLimits{136, 448, 128} : StackLimits{256, 512, 128};
-    return K == 9 ? StackLimits{80, 160, 128} : StackLimits{160, 384, 128};
+    // the larger stacks used before (768 and 512 entries).  OBB records are
+    // as large as 18-DOP records and take the 18-DOP sizes.
+    const bool big = bv != kBvAabb;
+    if (mode == MODE_DIST) return big ? StackLimits{136, 448, 128} : StackLimits{256, 512, 128};
+    return big ? StackLimits{80, 160, 128} : StackLimits{160, 384, 128};
 }
 
-uint32_t item_words(uint32_t K) { return words_of_item(K); }
+uint32_t item_words(uint32_t bv) { return words_of_item(bv_slabs(bv), bv == kBvObb); }
 
 hipError_t launch_query(const QueryArgs &q, const StackLimits &lim, hipStream_t s, uint32_t *pair_out,
                         uint32_t *pair_offsets)
@@ -1950,7 +2010,12 @@ hipError_t launch_decode_all(const DevModel &m, float *out, hipStream_t s)
     uint32_t items = bits_are_codes(m.bits) ? m.n_treelets : m.n_nodes;
     constexpr int F16 = (int)kBitsFp16;
     dim3 grid((items + threads - 1) / threads);
-    if (m.K == 3) {
+    if (m.bv == kBvObb) {
+        if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<3, 0, true>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<3, 8, true>), grid, dim3(threads), 0, s, m, out);
+        else if (m.bits == 16) hipLaunchKernelGGL((decode_all_kernel<3, 16, true>), grid, dim3(threads), 0, s, m, out);
+        else return hipErrorInvalidValue;
+    } else if (m.K == 3) {
         if (m.bits == 0) hipLaunchKernelGGL((decode_all_kernel<3, 0>), grid, dim3(threads), 0, s, m, out);
         else if (m.bits == 8) hipLaunchKernelGGL((decode_all_kernel<3, 8>), grid, dim3(threads), 0, s, m, out);
         else if (m.bits == kBitsFp16) hipLaunchKernelGGL((decode_all_kernel<3, F16>), grid, dim3(threads), 0, s, m, out);

@@ -1,7 +1,8 @@
 // Host (CPU) build of the leaf geometry that the traversal kernels run
 // (paper_2012_05348_amd/csrc/geom.h, compiled here as plain C++), so that
-// tests can drive the FP32 certified intersection test and the FP32 leaf
-// distance with adversarial triangle pairs and compare them with the oracle.
+// tests can drive the FP32 certified intersection test, the FP32 leaf
+// distance and the OBB box test with adversarial inputs and compare them
+// with exact references.
 // Built by the tests with g++ -O2 -ffp-contract=off (IEEE single precision,
 // fused multiply-adds only where the source writes them, as on the GPU).
 #include "../paper_2012_05348_amd/csrc/geom.h"
@@ -64,5 +65,19 @@ float gh_leaf_dist_f32(const float *pose12, const float *a9, const float *b9, in
 }
 
 float gh_dist_err(const float *pose12, float maxA, float maxB) { return dist_err_abs(pose12, maxA, maxB); }
+
+// the OBB test of the traversal: allowances of a pose, A's box placed by it,
+// and the gap test against B's box (sep > 0 proves them disjoint; lb is the
+// distance lower bound of distance queries)
+void gh_obb_test(const float *pose12, float rot_eps, float maxA, float maxB, const float *descA, const float *descB,
+                 float *sep, float *lb)
+{
+    const Pose P = pose(pose12);
+    float al[4], pa[20], s0, l0;
+    obb_allowances(pose12, rot_eps, maxA, maxB, al);
+    obb_place(P, descA, al[3], pa);
+    obb_gap<false>(pa, descB, al, sep, &l0);
+    obb_gap<true>(pa, descB, al, &s0, lb);
+}
 
 }  // extern "C"
