@@ -11,6 +11,7 @@ main measurement and reported as extra fields.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -41,9 +42,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def _models(cb, w, bits, dev):
+def _models(cb, w, bits, dev, bv=None):
     (va, ta), (vb, tb) = w.meshes()
-    bv = cb.AABB if w.bv == "aabb" else cb.DOP18
+    if bv is None:
+        bv = cb.AABB if w.bv == "aabb" else cb.DOP18
     ma = cb.Model.build(va, ta, bv=bv, branching=w.branching, leaf_size=w.leaf_size, bits=bits).to(dev)
     mb = cb.Model.build(vb, tb, bv=bv, branching=w.branching, leaf_size=w.leaf_size, bits=bits).to(dev)
     return ma, mb
@@ -89,9 +91,9 @@ def traversal_kernel_ms(cb, step, ws, calls):
     return out
 
 
-def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0):
+def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0, bv=None):
     import torch
-    ma, mb = _models(cb, w, bits, dev)
+    ma, mb = _models(cb, w, bits, dev, bv)
     P = torch.from_numpy(w.raw_poses()).to(dev)
     n = P.shape[0]
     ws = cb.workspace(ma, mb, n, flags, pair_capacity, dev)
@@ -117,9 +119,9 @@ def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0):
                 info=info, descriptor_bytes=info["descriptor_bytes"] + mb.info()["descriptor_bytes"], kern_ms=kern_ms)
 
 
-def run_distance(cb, w, bits, dev, steps, warmup, flags=0):
+def run_distance(cb, w, bits, dev, steps, warmup, flags=0, bv=None):
     import torch
-    ma, mb = _models(cb, w, bits, dev)
+    ma, mb = _models(cb, w, bits, dev, bv)
     P = torch.from_numpy(w.raw_poses()).to(dev)
     n = P.shape[0]
     ws = cb.workspace(ma, mb, n, 0, 0, dev)
@@ -134,7 +136,7 @@ def run_distance(cb, w, bits, dev, steps, warmup, flags=0):
     stats = cb.cbvh_stats(ws.buf)
     progress(f"  {steps} steps, {np.mean(dev_ms):.3f} ms/call, stats {stats}")
     kern_ms = traversal_kernel_ms(cb, step, ws.buf, min(steps, 10))
-    return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=bool((st == 0).all().item()),
+    return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=bool((st == 0).all().item()), dist=d.cpu().numpy(),
                 descriptor_bytes=ma.info()["descriptor_bytes"] + mb.info()["descriptor_bytes"], kern_ms=kern_ms)
 
 
@@ -506,6 +508,9 @@ def main():
                     help="also time the descriptor formats on N device copies of a 200k-triangle obstacle")
     ap.add_argument("--proximity-only", action="store_true",
                     help="time only the proximity distance workload (for kernel traces of the distance kernel)")
+    ap.add_argument("--proximity-dop18-only", action="store_true",
+                    help="time only the proximity workload's meshes as 18-DOP models (BF 8, leaf 4, 16-bit): "
+                         "the 18-DOP distance kernel, for its kernel traces and counters")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -524,6 +529,13 @@ def main():
         pr = run_distance(cb, w2, w2.bits, dev, args.steps, args.warmup)
         print(json.dumps({"workload": w2.name, "steps": args.steps, "warmup": args.warmup,
                           "proximity": summarize(pr, args.steps)}), flush=True)
+        return
+    if args.proximity_dop18_only:
+        w2 = dataclasses.replace(configs.WORKLOADS[2], bv="dop18", branching=8, leaf_size=4, bits=16)
+        pr = run_distance(cb, w2, w2.bits, dev, args.steps, args.warmup)
+        print(json.dumps({"workload": w2.name + " (as 18-DOP models, BF 8, leaf 4, 16-bit codes)",
+                          "steps": args.steps, "warmup": args.warmup, "proximity_dop18": summarize(pr, args.steps)}),
+              flush=True)
         return
     w = configs.WORKLOADS[1]
     main_r = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT)
@@ -598,9 +610,20 @@ def main():
         w0, w2 = configs.WORKLOADS[0], configs.WORKLOADS[2]
         tiny = run_collide(cb, w0, w0.bits, dev, 10, 2, cb.PAIRS, pair_capacity=1 << 20)
         out["tiny_pairs"] = summarize(tiny, 10)
+        prox = {}
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
-            pr = run_distance(cb, w2, bits, dev, 5, 1)
-            out[key] = summarize(pr, 5)
+            prox[key] = run_distance(cb, w2, bits, dev, 5, 1)
+            out[key] = summarize(prox[key], 5)
+        # oriented boxes in the same layout (the paper's future work): the
+        # scaled collision workload and the proximity workload as OBB models
+        # with the same trees and code widths
+        obb = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT, bv=cb.OBB)
+        out["obb"] = summarize(obb, args.steps)
+        out["obb"]["hits_equal"] = bool(np.array_equal(obb["hit"], main_r["hit"]))
+        pobb = run_distance(cb, w2, w2.bits, dev, 5, 1, bv=cb.OBB)
+        out["proximity_obb"] = summarize(pobb, 5)
+        out["proximity_obb"]["distances_equal"] = bool(np.array_equal(pobb["dist"].view(np.uint32),
+                                                                      prox["proximity"]["dist"].view(np.uint32)))
         from paper_2012_05348_amd import autotune
         out["treelet_sweep_scaled"] = run_treelet_sweep(cb, w, dev, (2048, 8192, 32768, autotune.WHOLE_TREE))
         out["batched"] = run_batched(cb, dev, 10, 2)

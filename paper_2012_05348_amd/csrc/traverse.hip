@@ -1385,46 +1385,78 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 my_nb = topo_leaf(my_tB) ? 1u : topo_count(my_tB);
                 if (MODE == MODE_DIST && ent_lb[idx] > tau) my_na = my_nb = 0;  // culled
             }
-            // inclusive prefix over lanes 0..PMAX-1 of (A records, B records, tests,
-            // expanded entries), packed in one word (8, 8, 10 and 6 bits)
             const uint32_t my_tk = my_na * my_nb;
-            const uint32_t my_pk =
-                lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16) | ((my_tk > 0 ? 1u : 0u) << 26)) : 0u;
-            uint32_t pk = my_pk;
-            static_assert(PMAX == 8, "the scan covers 8 lanes");
-            pk += row_shr<1>(pk);
-            pk += row_shr<2>(pk);
-            pk += row_shr<4>(pk);
-            const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = (pk >> 16) & 0x3FFu, inX = pk >> 26;
-            // with lane+1 entries popped the new frame sits on top of the frame of
-            // the next remaining entry (lane+1 read it): its level is one more.
-            // Frames are stacked in record space in level order, so the newest
-            // live frame (the top entry's) ends last: its end bounds where any
-            // new frame can start.
-            const uint32_t nx_e = row_shl<1>(my_e);
-            const uint32_t rem_l = top - 1u - lane;
-            const uint32_t nid_l = rem_l > 0 ? (nx_e >> (2 * REC_BITS)) + 1u : 0u;
+            // the newest live frame (the top entry's) ends last: its end bounds
+            // where any new frame can start
             const uint32_t f_top_end = lane_of(fe_v, (int)(uni(my_e) >> (2 * REC_BITS)));
-            const uint32_t nbase_l = rem_l > 0 ? f_top_end : 0u;
             // proximity queries dive one expansion at a time until a first leaf
             // distance exists: without a bound nothing is culled
             const bool dive = MODE == MODE_DIST && best32 == INFINITY;
-            // A frame stays live while any of its entries is pending, so a wider
-            // frame pins records for its whole subtree.  Where the record space
-            // cannot hold a full-depth descent (the host decides), more than
-            // one entry is popped only while the new frame leaves room for a
-            // frame of the top entry's size at every level a descent below it
-            // can still take (the two trees' depths minus the new frame's level).
-            const uint32_t levels = MA.depth + MB.depth;
-            const uint32_t reserve = (lane == 0 || !q.pop_reserve)
-                                         ? 0u
-                                         : lane_of(my_na + my_nb, 0) * (levels > nid_l ? levels - nid_l : 0u);
-            // culled entries (distance queries) cost nothing and may always go
-            const bool ok = lane < (uint32_t)PMAX && inX <= q.max_pop && lane < top && (!dive || lane == 0) && inA <= AMAX &&
-                            inA + inB <= (uint32_t)WAVE && inT <= TMAX && rem_l + inT <= lim.entries &&
-                            lq_count + inT <= lim.leafq && nid_l < (uint32_t)MAX_FRAMES &&
-                            nbase_l + inA + inB + reserve <= lim.records && nbase_l + inA + inB <= REC_MASK + 1u;
-            const uint32_t n_pop = (uint32_t)__builtin_ctzll(~__ballot(ok));  // leading lanes that fit
+            // One entry goes alone when no second one could join it (its tests
+            // fill the pass, as with two branching-factor-8 nodes, or the
+            // stack holds one entry): the fit checks then run on uniform values
+            // and the scan over the popped lanes is skipped.
+            const uint32_t tk0 = lane_of(my_tk, 0);
+            const bool single = tk0 > 0 && (dive || q.max_pop == 1 || top == 1 || tk0 + lane_of(my_tk, 1) > TMAX);
+            uint32_t n_pop, nA_tot, total_rec, tasks_tot, new_id, new_meta, pk = 0, my_pk = 0;
+            if (single) {
+                const uint32_t na0 = lane_of(my_na, 0), nb0 = lane_of(my_nb, 0), rem = top - 1u;
+                new_id = rem > 0 ? (lane_of(my_e, 1) >> (2 * REC_BITS)) + 1u : 0u;
+                const uint32_t nbase0 = rem > 0 ? f_top_end : 0u;
+                const bool ok0 = na0 <= AMAX && na0 + nb0 <= (uint32_t)WAVE && tk0 <= TMAX &&
+                                 rem + tk0 <= lim.entries && lq_count + tk0 <= lim.leafq &&
+                                 new_id < (uint32_t)MAX_FRAMES && nbase0 + na0 + nb0 <= lim.records &&
+                                 nbase0 + na0 + nb0 <= REC_MASK + 1u;
+                n_pop = ok0 ? 1u : 0u;
+                nA_tot = na0;
+                total_rec = na0 + nb0;
+                tasks_tot = tk0;
+                new_meta = meta_word(0u, na0, nb0, 0u);
+            } else {
+                // inclusive prefix over lanes 0..PMAX-1 of (A records, B records,
+                // tests, expanded entries), packed in one word (8, 8, 10 and 6 bits)
+                my_pk = lane < (uint32_t)PMAX ? (my_na | (my_nb << 8) | (my_tk << 16) | ((my_tk > 0 ? 1u : 0u) << 26))
+                                              : 0u;
+                pk = my_pk;
+                static_assert(PMAX == 8, "the scan covers 8 lanes");
+                pk += row_shr<1>(pk);
+                pk += row_shr<2>(pk);
+                pk += row_shr<4>(pk);
+                const uint32_t inA = pk & 0xFFu, inB = (pk >> 8) & 0xFFu, inT = (pk >> 16) & 0x3FFu, inX = pk >> 26;
+                // with lane+1 entries popped the new frame sits on top of the frame
+                // of the next remaining entry (lane+1 read it): its level is one more
+                const uint32_t nx_e = row_shl<1>(my_e);
+                const uint32_t rem_l = top - 1u - lane;
+                const uint32_t nid_l = rem_l > 0 ? (nx_e >> (2 * REC_BITS)) + 1u : 0u;
+                const uint32_t nbase_l = rem_l > 0 ? f_top_end : 0u;
+                // A frame stays live while any of its entries is pending, so a
+                // wider frame pins records for its whole subtree.  Where the record
+                // space cannot hold a full-depth descent (the host decides), more
+                // than one entry is popped only while the new frame leaves room for
+                // a frame of the top entry's size at every level a descent below
+                // it can still take (the two trees' depths minus the new frame's level).
+                const uint32_t levels = MA.depth + MB.depth;
+                const uint32_t reserve = (lane == 0 || !q.pop_reserve)
+                                             ? 0u
+                                             : lane_of(my_na + my_nb, 0) * (levels > nid_l ? levels - nid_l : 0u);
+                // culled entries (distance queries) cost nothing and may always go
+                const bool ok = lane < (uint32_t)PMAX && inX <= q.max_pop && lane < top && (!dive || lane == 0) &&
+                                inA <= AMAX && inA + inB <= (uint32_t)WAVE && inT <= TMAX &&
+                                rem_l + inT <= lim.entries && lq_count + inT <= lim.leafq &&
+                                nid_l < (uint32_t)MAX_FRAMES && nbase_l + inA + inB + reserve <= lim.records &&
+                                nbase_l + inA + inB <= REC_MASK + 1u;
+                n_pop = (uint32_t)__builtin_ctzll(~__ballot(ok));  // leading lanes that fit
+                const int last = n_pop > 0 ? (int)n_pop - 1 : 0;
+                nA_tot = lane_of(inA, last);
+                total_rec = nA_tot + lane_of(inB, last);
+                tasks_tot = lane_of(inT, last);
+                static_assert(TMAX < 1024u && PMAX < 64, "packed prefix fields");
+                new_id = lane_of(nid_l, last);
+                // the new frame's entries (culled ones stay, with no tasks): first
+                // A record and first B record in the frame, B's child count, first task
+                const uint32_t ex = pk - my_pk;  // exclusive prefix
+                new_meta = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
+            }
             if (n_pop == 0) {
                 // not even the top entry fits the LDS state: hand every pending
                 // pair (node pairs with their decoded bounds, and queued leaf
@@ -1438,20 +1470,11 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 }
                 break;
             }
-            const int last = (int)n_pop - 1;
-            const uint32_t nA_tot = lane_of(inA, last), total_rec = nA_tot + lane_of(inB, last);
-            const uint32_t tasks_tot = lane_of(inT, last);
-            static_assert(TMAX < 1024u && PMAX < 64, "packed prefix fields");
-            const uint32_t new_id = lane_of(nid_l, last);
             top -= n_pop;
             // the new frame starts where the frame of the next remaining entry ends
             const uint32_t new_base = top > 0 ? lane_of(fe_v, (int)new_id - 1) : 0u;
-            const uint32_t ns = __popcll(__ballot(lane < n_pop && my_tk > 0));
+            const uint32_t ns = single ? 1u : __popcll(__ballot(lane < n_pop && my_tk > 0));
             if (ns == 0) continue;
-            // the new frame's entries (culled ones stay, with no tasks): first
-            // A record and first B record in the frame, B's child count, first task
-            const uint32_t ex = pk - my_pk;  // exclusive prefix
-            const uint32_t new_meta = meta_word(ex & 0xFFu, nA_tot + ((ex >> 8) & 0xFFu), my_nb, (ex >> 16) & 0x3FFu);
             // decode: one lane per new record, A records first, then B records.
             // A record's entry is the popped lane whose run of records holds
             // it (with one popped entry, lane 0's, uniform); its parent data
