@@ -74,9 +74,9 @@ cbvh::DevModel dev_view(const cbvh_model *m, const void *dev)
     return d;
 }
 
-cbvh::StackLimits current_limits(uint32_t bv, int mode)
+cbvh::StackLimits current_limits(uint32_t bv, int mode, uint32_t branching)
 {
-    cbvh::StackLimits l = cbvh::default_limits(bv, mode);
+    cbvh::StackLimits l = cbvh::default_limits(bv, mode, branching);
     uint32_t e = g_limit_entries.load(), r = g_limit_records.load();
     if (e) l.entries = e;
     if (r) l.records = r;
@@ -211,7 +211,7 @@ cbvh_status run_query(const cbvh_model *a, const void *a_dev, const cbvh_model *
     q.ws.pair_cnt = (uint32_t *)(w + plan.pair_cnt);
     q.ws.pair_cursor = (uint32_t *)(w + plan.pair_cursor);
     q.ws.pair_keys = (unsigned long long *)(w + plan.pair_keys);
-    cbvh::StackLimits lim = current_limits(a->hdr.bv, mode);
+    cbvh::StackLimits lim = current_limits(a->hdr.bv, mode, q.A.branching > q.B.branching ? q.A.branching : q.B.branching);
     hipError_t e = cbvh::launch_query(q, lim, (hipStream_t)stream, pairs, pair_offsets);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     return CBVH_OK;

@@ -123,7 +123,8 @@ struct QueryArgs {
 
 // Bytes of one wave's traversal state for a BV type, a mode and limits.
 size_t wave_state_bytes(uint32_t bv, int mode, const StackLimits &lim);
-StackLimits default_limits(uint32_t bv, int mode);
+// default limits for a BV type, a mode and the models' largest branching factor
+StackLimits default_limits(uint32_t bv, int mode, uint32_t branching);
 uint32_t item_words(uint32_t bv);
 
 // Enqueue the whole query on `stream`: init, the traversal, and the finalize

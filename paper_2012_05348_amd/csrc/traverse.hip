@@ -1979,14 +1979,16 @@ size_t wave_state_bytes(uint32_t bv, int mode, const StackLimits &lim)
     return make_layout(bv_slabs(bv), mode, lim, bv == kBvObb).total;
 }
 
-StackLimits default_limits(uint32_t bv, int mode)
+StackLimits default_limits(uint32_t bv, int mode, uint32_t branching)
 {
     // branch-and-bound keeps many more pairs pending than collision queries;
     // the sizes let 10 waves (AABB) or 8 waves (18-DOP, the most its
     // registers allow) fit a CU, about 5 % faster than 8 and 7 waves with
     // the larger stacks used before (768 and 512 entries).  OBB records are
-    // as large as 18-DOP records and take the 18-DOP sizes.
-    const bool big = bv != kBvAabb;
+    // as large as 18-DOP records: OBB models of branching factor 8 take the
+    // 18-DOP sizes, narrower ones (deeper trees, whose descents need more
+    // records) the AABB sizes.
+    const bool big = bv == kBvDop18 || (bv == kBvObb && branching >= 8);
     if (mode == MODE_DIST) return big ? StackLimits{136, 448, 128} : StackLimits{256, 512, 128};
     return big ? StackLimits{80, 160, 128} : StackLimits{160, 384, 128};
 }

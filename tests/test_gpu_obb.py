@@ -14,7 +14,9 @@ models do:
 - small stacks that force work hand-over between waves (items carry the
   frames): pair lists still exact;
 - the scaled workload's meshes as OBB models: booleans on all 16,384 poses
-  equal the 18-DOP models' and the oracle's on a 512-pose sample.
+  equal the 18-DOP models' and the oracle's on a 512-pose sample;
+- the proximity workload's meshes as OBB models: every pose completes, with
+  distances bit-identical to the AABB models' on all 4,096 poses.
 """
 import sys
 
@@ -180,3 +182,21 @@ def test_obb_scaled_booleans_equal_dop18_and_oracle():
     ref, _ = oracle.collide_batch(A, B, P[idx][ok])
     assert ok.sum() > 400
     assert np.array_equal(ho[idx][ok], ref)
+
+
+def test_obb_proximity_distances_equal_aabb_on_every_pose():
+    """The proximity workload (4,096 poses, 50k-triangle meshes, branching 4,
+    8-bit codes) as OBB models: every pose completes and its distance is
+    bit-identical to the AABB models' (which the oracle checks on every pose
+    in the parity suite)."""
+    w = configs.WORKLOADS[2]
+    P = torch.from_numpy(w.raw_poses()).to(DEV)
+    (va, ta), (vb, tb) = W.meshes(2)
+    kw = dict(branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    mo = [cb.Model.build(v, t, bv=cb.OBB, **kw).to(DEV) for v, t in ((va, ta), (vb, tb))]
+    ma = [cb.Model.build(v, t, bv=cb.AABB, **kw).to(DEV) for v, t in ((va, ta), (vb, tb))]
+    _log("obb proximity distances")
+    do, so = cb.distance(mo[0], mo[1], P)
+    da, sa = cb.distance(ma[0], ma[1], P)
+    assert (so.cpu().numpy() == 0).all() and (sa.cpu().numpy() == 0).all()
+    assert np.array_equal(do.cpu().numpy().view(np.uint32), da.cpu().numpy().view(np.uint32))
