@@ -309,11 +309,11 @@ def run_serving(cb, dev, n_requests=1500):
     from synth import configs
     w = configs.SERVING
     kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
-    # the batched workload's tuned pick (build parameters and launch knobs), where one is stored
-    from paper_2012_05348_amd import autotune
-    cfg = autotune.load(configs.BATCHED.name)
-    kw.update(autotune.build_kwargs(cfg, w.branching))
-    progress(f"serving: building {w.n_obstacles} resident obstacle models (tuned pick {cfg})")
+    # the library's defaults: the batched workload's tuned pick (one launch at
+    # a time) made the serving loop's latencies worse where launches share the
+    # GPU, so it is not applied here
+    cfg = None
+    progress(f"serving: building {w.n_obstacles} resident obstacle models")
     link = cb.Model.build(*w.link_mesh(), **kw).to(dev)
     oset = cb.Obstacles([cb.Model.build(*w.obstacle_mesh(i), **kw).to(dev) for i in range(w.n_obstacles)], dev)
     srv = serve.Server(link, oset, dev, launch_cfg=cfg)
@@ -323,9 +323,11 @@ def run_serving(cb, dev, n_requests=1500):
     sat_req = serve.make_requests(n_requests, np.inf, w.n_obstacles, rng)
     sat = srv.run(sat_req, realtime=False)
     rate = sat["requests_per_sec"]
-    out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests, "tuned": cfg,
-           "saturation": {k: sat[k] for k in ("poses_per_sec", "requests_per_sec", "launches", "p50_ms", "p99_ms")}}
+    out = {"obstacles": w.n_obstacles, "max_poses_per_launch": srv.max_poses, "requests": n_requests,
+           "saturation": {k: sat[k] for k in ("poses_per_sec", "requests_per_sec", "launches", "retry_launches",
+                                              "p50_ms", "p99_ms")}}
     out["saturation"]["status_ok"] = bool((sat["status"] == 0).all())
+    out["saturation"]["status_counts"] = np.bincount(sat["status"], minlength=6).tolist()
     # each served request against its plain query run alone (the judge of the batched path)
     progress("serving: every request of the saturation run against its plain query")
     import torch
@@ -348,7 +350,8 @@ def run_serving(cb, dev, n_requests=1500):
         ok = bool((r["status"] == 0).all())
         out[f"load_{int(frac * 100)}"] = {"offered_requests_per_sec": frac * rate, "poses_per_sec": r["poses_per_sec"],
                                           "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "launches": r["launches"],
-                                          "status_ok": ok}
+                                          "retry_launches": r["retry_launches"], "status_ok": ok,
+                                          "status_counts": np.bincount(r["status"], minlength=6).tolist()}
         progress(f"  load {frac:.0%}: p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms")
     return out
 

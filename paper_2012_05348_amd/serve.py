@@ -21,8 +21,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (EARLY_EXIT, POSE_INCOMPLETE, Model, Obstacles, cbvh_collide_batch, cbvh_distance_batch,
-               cbvh_workspace_bytes, _aligned_empty)
+from . import (EARLY_EXIT, NO_SPLIT, POSE_INCOMPLETE, POSE_STACK_OVERFLOW, Model, Obstacles, cbvh_collide_batch,
+               cbvh_distance_batch, cbvh_workspace_bytes, _aligned_empty)
+
+# times a pose flagged CBVH_POSE_STACK_OVERFLOW is run again before its flag is kept
+RETRIES = 2
 
 COLLIDE, DISTANCE = 0, 1
 
@@ -115,7 +118,11 @@ class _Slot:
         self.hout = torch.empty(max_poses, dtype=self.out.dtype).pin_memory()
         self.hstatus = torch.empty(max_poses, dtype=torch.uint8).pin_memory()
         self.event = torch.cuda.Event()
-        self.busy = None  # [(request, first pose in the launch, count)] while a launch is in flight
+        # while a launch is in flight: the global pose index of each of its
+        # poses, in launch order, and how many times they have been retried
+        self.busy = None
+        self.gidx = None
+        self.tries = 0
 
 
 class Server:
@@ -128,8 +135,12 @@ class Server:
 
     def __init__(self, link: Model, obstacles: Obstacles, device="cuda", slots_per_kind=2,
                  memory_budget=2 << 30, max_poses=None, launch_cap=16384, distance_cap=None, small_max=256,
-                 launch_cfg=None):
+                 launch_cfg=None, first_flags=0):
         self.link, self.obstacles, self.device = link, obstacles, device
+        # extra query flags of a pose's first launch (CBVH_NO_SPLIT keeps it in
+        # one wavefront); a pose run again after a stack overflow always may
+        # hand work over
+        self.first_flags = first_flags
         # launch knobs of a tuned configuration (autotune.launch_env), applied to every launch
         self.launch_cfg = launch_cfg
         # the largest launch that lets every slot's workspace fit the budget
@@ -173,36 +184,71 @@ class Server:
         hit = np.zeros(N, dtype=np.uint8)
         dist = np.full(N, np.nan, dtype=np.float32)
         status = np.zeros(N, dtype=np.uint8)
+        req_of = np.repeat(np.arange(R), req.count)  # request of each global pose
+        pending = req.count.astype(np.int64).copy()  # poses of each request without a final answer
         # per kind: its requests in arrival order, which are admitted, and the first not yet admitted
         queue = {k: {"rs": np.nonzero(req.kind == k)[0], "admitted": None, "head": 0} for k in (COLLIDE, DISTANCE)}
         for Q in queue.values():
             Q["admitted"] = np.zeros(len(Q["rs"]), dtype=bool)
         done_at = np.full(R, np.nan)
-        n_launch = 0
+        n_launch = n_retry = 0
         max_batch = 0
         t0 = time.perf_counter()
         remaining = R
+
+        def launch(s, gidx, tries):
+            """Stage the poses gidx (global indices) in the slot and launch them."""
+            n = len(gidx)
+            flags = self.first_flags if tries == 0 else self.first_flags & ~NO_SPLIT
+            s.hP.numpy()[:n] = req.poses[gidx]
+            s.hobj.numpy()[:n] = req.obstacle[req_of[gidx]]
+            with torch.cuda.stream(s.stream):
+                s.P[:n].copy_(s.hP[:n], non_blocking=True)
+                s.obj[:n].copy_(s.hobj[:n], non_blocking=True)
+                if s.kind == COLLIDE:
+                    cbvh_collide_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n,
+                                       EARLY_EXIT | flags, s.out, s.status, s.ws, stream=s.stream)
+                else:
+                    cbvh_distance_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n, flags,
+                                        s.out, s.status, s.ws, stream=s.stream)
+                s.hout[:n].copy_(s.out[:n], non_blocking=True)
+                s.hstatus[:n].copy_(s.status[:n], non_blocking=True)
+                s.event.record(s.stream)
+            s.gidx, s.tries, s.busy = gidx, tries, True
+
         while remaining:
             now = time.perf_counter() - t0
             progressed = False
             for s in self.slots:
                 if s.busy is not None and s.event.query():
                     t_done = time.perf_counter() - t0
-                    out_np, st_np = s.hout.numpy(), s.hstatus.numpy()
-                    n_done = sum(c for _, _, c in s.busy)
-                    if (st_np[:n_done] == POSE_INCOMPLETE).any():
+                    gidx = s.gidx
+                    n_done = len(gidx)
+                    out_np, st_np = s.hout.numpy()[:n_done], s.hstatus.numpy()[:n_done]
+                    if (st_np == POSE_INCOMPLETE).any():
                         # a wavefront gave up waiting for handed-over work: this
                         # launch's answers cannot be trusted
                         raise RuntimeError("a launch gave up waiting for handed-over work (device wait limit); "
-                                           f"results of its {len(s.busy)} requests are incomplete")
-                    for r, off, c in s.busy:
-                        sl = slice(req.first[r], req.first[r] + c)
-                        (hit if s.kind == COLLIDE else dist)[sl] = out_np[off:off + c]
-                        status[sl] = st_np[off:off + c]
-                        done_at[r] = t_done
-                    remaining -= len(s.busy)
+                                           f"results of its {n_done} poses are incomplete")
+                    (hit if s.kind == COLLIDE else dist)[gidx] = out_np
+                    status[gidx] = st_np
+                    # a pose whose traversal state outgrew its wavefront where
+                    # nobody could take its pending pairs (its launch's helper
+                    # waves had already left, as can happen when launches share
+                    # the GPU) is run again in a launch of its own
+                    again = (st_np == POSE_STACK_OVERFLOW) & (s.tries < RETRIES)
+                    final = gidx[~again]
+                    np.subtract.at(pending, req_of[final], 1)
+                    for r in np.unique(req_of[final]):
+                        if pending[r] == 0:
+                            done_at[r] = t_done
+                            remaining -= 1
                     s.busy = None
                     progressed = True
+                    if again.any():
+                        launch(s, gidx[again], s.tries + 1)
+                        n_retry += 1
+                        continue
                 if s.busy is not None:
                     continue
                 Q = queue[s.kind]
@@ -226,24 +272,9 @@ class Server:
                     n += c
                 if not chosen:
                     continue
-                hP, hobj = s.hP.numpy(), s.hobj.numpy()
-                for i, r, off, c in chosen:
-                    hP[off:off + c] = req.poses[req.first[r]:req.first[r] + c]
-                    hobj[off:off + c] = req.obstacle[r]
+                for i, _, _, _ in chosen:
                     adm[i] = True
-                with torch.cuda.stream(s.stream):
-                    s.P[:n].copy_(s.hP[:n], non_blocking=True)
-                    s.obj[:n].copy_(s.hobj[:n], non_blocking=True)
-                    if s.kind == COLLIDE:
-                        cbvh_collide_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n,
-                                           EARLY_EXIT, s.out, s.status, s.ws, stream=s.stream)
-                    else:
-                        cbvh_distance_batch(self.link.handle, self.link.dev, self.obstacles.handle, s.P, s.obj, n, 0,
-                                            s.out, s.status, s.ws, stream=s.stream)
-                    s.hout[:n].copy_(s.out[:n], non_blocking=True)
-                    s.hstatus[:n].copy_(s.status[:n], non_blocking=True)
-                    s.event.record(s.stream)
-                s.busy = [(r, off, c) for _, r, off, c in chosen]
+                launch(s, np.concatenate([np.arange(req.first[r], req.first[r] + c) for _, r, _, c in chosen]), 0)
                 n_launch += 1
                 max_batch = max(max_batch, n)
                 progressed = True
@@ -254,5 +285,6 @@ class Server:
         lat = done_at - req.arrival
         return {"latency_s": lat, "hit": hit, "dist": dist, "status": status, "makespan_s": makespan,
                 "poses_per_sec": N / makespan, "requests_per_sec": R / makespan, "launches": n_launch,
+                "retry_launches": n_retry,
                 "largest_launch": max_batch, "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3)}

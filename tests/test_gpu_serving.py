@@ -157,3 +157,38 @@ def test_an_incomplete_launch_fails_the_run(server):
     srv2 = serve.Server(link, cb.Obstacles(obs, DEV), DEV, slots_per_kind=1, max_poses=600)
     res = srv2.run(req, realtime=False)
     assert (res["status"] == 0).all()
+
+
+def test_poses_that_overflow_their_stack_are_run_again():
+    """Small per-wave stacks, and first launches that keep every pose in one
+    wavefront (no hand-over), make poses overflow (CBVH_POSE_STACK_OVERFLOW);
+    the loop runs those poses again, with hand-over allowed, so every
+    request still gets its plain query's answer.  AABB models of branching
+    factor 4 (16 child pairs per expansion), so that hand-over with these
+    stacks makes progress."""
+    w = SMALL
+    kw = dict(bv=cb.AABB, branching=4, leaf_size=w.leaf_size, bits=8)
+    link = cb.Model.build(*w.link_mesh(), **kw).to(DEV)
+    obs = [cb.Model.build(*w.obstacle_mesh(i), **kw).to(DEV) for i in range(w.n_obstacles)]
+    srv = serve.Server(link, cb.Obstacles(obs, DEV), DEV, slots_per_kind=1, max_poses=600,
+                       first_flags=cb.NO_SPLIT)
+    req = serve.make_requests(24, np.inf, len(obs), np.random.default_rng(31), batch_max=300)
+    try:
+        # 64 records hold about half of a full descent of these trees: poses
+        # that reach the leaves overflow without hand-over
+        cb.cbvh_set_stack_limits(entries=256, records=64)
+        res = srv.run(req, realtime=False)
+        alone = [_alone(link, obs, req, r) for r in range(len(req))]
+    finally:
+        cb.cbvh_set_stack_limits(0, 0)
+    _log(f"stack-overflow retries: {res['retry_launches']} retry launches, statuses "
+         f"{np.bincount(res['status'], minlength=6).tolist()}")
+    assert res["retry_launches"] > 0
+    assert (res["status"] == 0).all()
+    for r in range(len(req)):
+        sl = slice(req.first[r], req.first[r] + req.count[r])
+        got = res["hit"][sl] if req.kind[r] == serve.COLLIDE else res["dist"][sl]
+        ref, st = alone[r]
+        assert (st == 0).all()
+        assert np.array_equal(got.view(np.uint32) if got.dtype == np.float32 else got,
+                              ref.view(np.uint32) if ref.dtype == np.float32 else ref)
