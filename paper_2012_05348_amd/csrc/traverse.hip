@@ -877,6 +877,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         float best32 = INFINITY;
         double best64 = INFINITY;
         uint32_t next_look = kDonatePeriod, next_sync = kSyncPeriod;
+        // this unit's node-step statistics, added to the wave's counters when it ends
+        uint32_t st_tests = 0, st_exp = 0, st_steps = 0, st_max_ent = 0, st_max_rec = 0;
+        unsigned long long st_bytes = 0;
         if (!from_item) {
             // root frame: record 0 = A's root, record 1 = B's root; the root pair is tested first
             if (lane < 2) {
@@ -1122,10 +1125,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 }
                 lq_count += n_ll;
                 top += n_nd;
-                if (lane == 0) {
-                    ctr_add(C_BV_TESTS, f_tasks);
-                    ctr_max(C_MAX_ENTRIES, top);
-                }
+                st_tests += f_tasks;
+                st_max_ent = max(st_max_ent, top);
                 wave_sync();
             }
             if (MODE == MODE_BOOL && hit) break;
@@ -1508,10 +1509,8 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             {
                 // algorithmic bytes: topology word and codes of every decoded child
                 const bool from_node = dec && !topo_leaf(sideA ? g_pA : g_pB);
-                const unsigned long long nbytes =
-                    (unsigned long long)__popcll(__ballot(from_node && sideA)) * code_bytes_A +
-                    (unsigned long long)__popcll(__ballot(from_node && !sideA)) * code_bytes_B;
-                if (lane == 0) ctr_add(C_NODE_BYTES, nbytes);
+                st_bytes += (unsigned long long)__popcll(__ballot(from_node && sideA)) * code_bytes_A +
+                            (unsigned long long)__popcll(__ballot(from_node && !sideA)) * code_bytes_B;
             }
             if (dec) {
                 const uint32_t c = r - off;
@@ -1538,11 +1537,9 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 if (sideA) prep_A(lane, my_b, my_topo);
             }
             if (lane == new_id) fe_v = new_base + total_rec;
-            if (lane == 0) {
-                ctr_add(C_EXPANSIONS, ns);
-                ctr_add(C_NODE_STEPS, 1);
-                ctr_max(C_MAX_RECORDS, new_base + total_rec);
-            }
+            st_exp += ns;
+            st_steps++;
+            st_max_rec = max(st_max_rec, new_base + total_rec);
             wave_sync();
             // the new frame becomes the current one
             f_base = new_base;
@@ -1553,7 +1550,15 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             f_meta = new_meta;
             have_frame = true;
         }
-        if (lane == 0) ctr_max(C_MAX_POSE_STEPS, steps);
+        if (lane == 0) {
+            ctr_max(C_MAX_POSE_STEPS, steps);
+            ctr_add(C_BV_TESTS, st_tests);
+            ctr_max(C_MAX_ENTRIES, st_max_ent);
+            ctr_add(C_NODE_BYTES, st_bytes);
+            ctr_add(C_EXPANSIONS, st_exp);
+            ctr_add(C_NODE_STEPS, st_steps);
+            ctr_max(C_MAX_RECORDS, st_max_rec);
+        }
         if (q.prio_steps && steps >= q.prio_steps) __builtin_amdgcn_s_setprio(0);
 
         // ---- results of this unit ----
