@@ -1868,8 +1868,10 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     // as many waves as fit on a CU at once (registers and LDS): the waves
     // are persistent, so every one of them must be resident
     int occ = 0;
-    // workgroup shape: waves per workgroup (independent waves; 1, 2 or 4)
-    uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", 1u);
+    // workgroup shape: waves per workgroup (independent waves; 1, 2 or 4).
+    // Distance queries default to two (5 % faster on the AABB proximity
+    // query, 1.5 % on 18-DOP models, in paired runs), collision queries to one.
+    uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", MODE == MODE_DIST ? 2u : 1u);
     wpg = wpg >= 4 ? 4u : wpg >= 2 ? 2u : 1u;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE, OBB>),
                                                      WAVE * wpg, L.total * wpg) != hipSuccess || occ < 1) {

@@ -550,12 +550,13 @@ def test_wait_limit_timeout_flags_every_pose(query):
         assert (np.abs(got[pos] - ref[pos]) / ref[pos]).max() <= 1e-5
 
 
-@pytest.mark.parametrize("wpg", ["2", "4"])
+@pytest.mark.parametrize("wpg", ["1", "2", "4"])
 def test_workgroup_shape_keeps_answers(wpg, monkeypatch):
-    """Several independent waves per workgroup (the launch's workgroup shape,
-    a tuning knob) change how waves are placed, never an answer: collision
+    """Independent waves per workgroup (the launch's workgroup shape, a
+    tuning knob; the defaults are one for collision and two for distance
+    queries) change how waves are placed, never an answer: collision
     booleans of the scaled workload and distances of the proximity workload
-    equal the one-wave-per-workgroup launch bitwise."""
+    equal the default launch's bitwise."""
     wc, wd = configs.WORKLOADS[1], configs.WORKLOADS[2]
     Pc = torch.from_numpy(wc.raw_poses(4096)).to(DEV)
     Pd = torch.from_numpy(wd.raw_poses(1024)).to(DEV)
