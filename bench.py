@@ -309,9 +309,9 @@ def run_serving(cb, dev, n_requests=1500):
     from synth import configs
     w = configs.SERVING
     kw = dict(bv=cb.DOP18, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
-    # the library's defaults: the batched workload's tuned pick (one launch at
-    # a time) made the serving loop's latencies worse where launches share the
-    # GPU, so it is not applied here
+    # the serving loop's own launch defaults (one wave per workgroup): the
+    # batched workload's tuned pick (one launch at a time) made its latencies
+    # worse where launches share the GPU, so it is not applied here
     cfg = None
     progress(f"serving: building {w.n_obstacles} resident obstacle models")
     link = cb.Model.build(*w.link_mesh(), **kw).to(dev)

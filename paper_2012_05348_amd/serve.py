@@ -141,8 +141,12 @@ class Server:
         # one wavefront); a pose run again after a stack overflow always may
         # hand work over
         self.first_flags = first_flags
-        # launch knobs of a tuned configuration (autotune.launch_env), applied to every launch
-        self.launch_cfg = launch_cfg
+        # launch knobs (autotune.launch_env), applied to every launch.  By
+        # default one wave per workgroup: the slots' launches share the GPU,
+        # and workgroups of several waves, which the library takes for
+        # distance queries otherwise, then made loaded latencies several
+        # times worse and the saturation rate lower
+        self.launch_cfg = {"waves_per_group": 1} if launch_cfg is None else launch_cfg
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
             lo, hi = 4096, 1 << 22
