@@ -1867,17 +1867,24 @@ hipError_t launch_traverse(const QueryArgs &q, const StackLimits &lim, hipStream
     if (cus < 1) cus = 256;
     // as many waves as fit on a CU at once (registers and LDS): the waves
     // are persistent, so every one of them must be resident
-    int occ = 0;
+    auto waves_fitting = [&](uint32_t wpg) -> uint32_t {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE, OBB>),
+                                                         WAVE * wpg, L.total * wpg) != hipSuccess || occ < 1) {
+            (void)hipGetLastError();  // clear a failed query's error; fall back to the LDS bound
+            occ = (int)(160u * 1024u / (L.total * wpg + 256u));
+        }
+        return (uint32_t)max(occ, 1) * wpg;
+    };
     // workgroup shape: waves per workgroup (independent waves; 1, 2 or 4).
-    // Distance queries default to two (5 % faster on the AABB proximity
-    // query, 1.5 % on 18-DOP models, in paired runs), collision queries to one.
-    uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", MODE == MODE_DIST ? 2u : 1u);
+    // Distance queries take two where that keeps as many waves resident (5 %
+    // faster on the AABB proximity query, 1.5 % on 18-DOP models, in paired
+    // runs; OBB models, whose larger LDS state then fits fewer waves, were
+    // 24 % slower), collision queries one.
+    uint32_t wpg = env_u32("CBVH_WAVES_PER_GROUP", 0u);
+    if (wpg == 0) wpg = (MODE == MODE_DIST && waves_fitting(2) >= waves_fitting(1)) ? 2u : 1u;
     wpg = wpg >= 4 ? 4u : wpg >= 2 ? 2u : 1u;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(traverse_kernel<K, BITS, MODE, OBB>),
-                                                     WAVE * wpg, L.total * wpg) != hipSuccess || occ < 1) {
-        (void)hipGetLastError();  // clear a failed query's error; fall back to the LDS bound
-        occ = (int)(160u * 1024u / (L.total * wpg + 256u));
-    }
+    const uint32_t occ = waves_fitting(wpg) / wpg;
     uint32_t per_cu = min((uint32_t)occ * wpg, env_u32("CBVH_WAVES_PER_CU", 32u));
     if (per_cu > 32) per_cu = 32;
     per_cu = max(per_cu / wpg, 1u) * wpg;
