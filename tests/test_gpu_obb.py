@@ -16,7 +16,9 @@ models do:
 - the scaled workload's meshes as OBB models: booleans on all 16,384 poses
   equal the 18-DOP models' and the oracle's on a 512-pose sample;
 - the proximity workload's meshes as OBB models: every pose completes, with
-  distances bit-identical to the AABB models' on all 4,096 poses.
+  distances bit-identical to the AABB models' on all 4,096 poses;
+- batched queries against an obstacle set of OBB models, and the
+  allocation-free entry point: equal to the plain queries.
 """
 import sys
 
@@ -200,3 +202,45 @@ def test_obb_proximity_distances_equal_aabb_on_every_pose():
     da, sa = cb.distance(ma[0], ma[1], P)
     assert (so.cpu().numpy() == 0).all() and (sa.cpu().numpy() == 0).all()
     assert np.array_equal(do.cpu().numpy().view(np.uint32), da.cpu().numpy().view(np.uint32))
+
+
+def test_obb_batched_queries_equal_plain_queries():
+    """A moving OBB model against an obstacle set of OBB models of uneven
+    size in one launch (items of other poses carry their own obstacle's
+    frames): booleans and distances equal the plain per-obstacle queries,
+    and the allocation-free entry point's booleans equal the plain ones."""
+    w = configs.BatchedWorkload(n_obstacles=6, tri_max=20000, min_poses=1500)
+    kw = dict(bv=cb.OBB, branching=w.branching, leaf_size=w.leaf_size, bits=w.bits)
+    link = cb.Model.build(*w.link_mesh(), **kw).to(DEV)
+    obs = [cb.Model.build(*w.obstacle_mesh(i), **kw).to(DEV) for i in range(w.n_obstacles)]
+    P, obj = w.raw_poses()
+    Pd, od = torch.from_numpy(P).to(DEV), torch.from_numpy(obj.astype(np.int32)).to(DEV)
+    oset = cb.Obstacles(obs, DEV)
+    _log(f"obb batched: {len(obs)} obstacles, {len(P)} poses")
+    hit, st = cb.collide_batch(link, oset, Pd, od)
+    sel = np.arange(0, len(P), 3)
+    d, dst = cb.distance_batch(link, oset, torch.from_numpy(P[sel]).to(DEV),
+                               torch.from_numpy(obj[sel].astype(np.int32)).to(DEV))
+    assert (st.cpu().numpy() == 0).all() and (dst.cpu().numpy() == 0).all()
+    hit, d = hit.cpu().numpy(), d.cpu().numpy()
+    assert 0 < hit.sum() < len(hit)
+    for k, m in enumerate(obs):
+        idx = np.nonzero(obj == k)[0]
+        if len(idx) == 0:
+            continue
+        h, hs = cb.collide(link, m, torch.from_numpy(P[idx]).to(DEV))
+        assert (hs.cpu().numpy() == 0).all()
+        assert np.array_equal(hit[idx], h.cpu().numpy())
+        n = len(idx)
+        hst = torch.empty(n, dtype=torch.uint8, device=DEV)
+        sst = torch.empty(n, dtype=torch.uint8, device=DEV)
+        cb.cbvh_collide_static(link.handle, link.dev, m.handle, m.dev, torch.from_numpy(P[idx]).to(DEV), n,
+                               cb.EARLY_EXIT, hst, sst)
+        torch.cuda.synchronize()
+        assert (sst.cpu().numpy() == 0).all()
+        assert np.array_equal(hst.cpu().numpy(), h.cpu().numpy())
+        ids = np.nonzero(obj[sel] == k)[0]
+        if len(ids):
+            dd, ds = cb.distance(link, m, torch.from_numpy(P[sel][ids]).to(DEV))
+            assert (ds.cpu().numpy() == 0).all()
+            assert np.array_equal(d[ids].view(np.uint32), dd.cpu().numpy().view(np.uint32))
