@@ -3,20 +3,25 @@
 // Collision Detection & Proximity Query"), one wavefront per pose.
 //
 // Per wave, in LDS:
-//   records  decoded BVs (topology word + 2K float bounds) grouped in LIFO
-//            frames; a frame holds the children decoded by one node step
-//            and is the predictor for the next level's codes;
+//   records  decoded BVs (topology word + 2K float bounds; an OBB's whole
+//            descriptor with its frame) grouped in LIFO frames; a frame
+//            holds the children decoded by one node step and is the
+//            predictor for the next level's codes;
 //   entries  pending node pairs (A record, B record, frame id), LIFO;
 //   leafq    pending leaf pairs (two leaf topology words);
-//   ta       A's records of the current frame moved into B's frame.
+//   ta       A's records of the current frame moved into B's frame (OBB
+//            models: A's boxes placed by the pose, in tsph);
+//   pose     the current pose and its rounding allowances; statistics.
 //
 // Node step: pop up to 8 entries whose child-pair tests fit in 64 lanes,
 // decode the children (one lane per child) into a new frame, transform A's
 // children with the pose's support-function coefficients, test every child
 // pair in its own lane (Algorithm 1's "a_i and b_j intersect", or a BV
 // distance lower bound), and compact the survivors with ballot + mbcnt into
-// the entry stack (inner pairs) or the leaf queue (leaf pairs).
-// Leaf step: up to 64 triangle pairs, one per lane (checkPrimitives).
+// the entry stack (inner pairs; the most promising one on top) or the leaf
+// queue (leaf pairs).
+// Leaf step: up to 64 triangle pairs, one per lane (checkPrimitives);
+// pairs that FP32 cannot decide go to a separate FP64 kernel.
 //
 // A pose whose next node step would not fit its LDS state hands all of its
 // pending pairs to the device-wide item queue (other waves finish them);
