@@ -1495,10 +1495,13 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             } else {
                 uint32_t e = 0;
 #pragma unroll
-                for (int s = 0; s < PMAX; s++) {
+                // (the last popped entry's run ends past every record of its
+                // side, so only the first n_pop - 1 ends are compared)
+                for (int s = 0; s < PMAX - 1; s++) {
+                    if ((uint32_t)s + 1u >= n_pop) break;
                     const uint32_t w = lane_of(pk, s);
                     const uint32_t end = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
-                    if ((uint32_t)s < n_pop && end <= r) {
+                    if (end <= r) {
                         e = (uint32_t)s + 1u;
                         off = end;
                     }
