@@ -407,6 +407,64 @@ CBVH_GEOM_INLINE void obb_gap(const float *pa, const float *bB, const float *al,
         const float gs = sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz))) * (1.0f - 0x1p-20f) - pa[17] -
                          radB - 2.0f * e_obb;
         lb = fmaxf(lb, gs);
+        // The gap along one direction found by alternating projections: B's
+        // point nearest to A's centre, A's point nearest to that, B's point
+        // nearest to that, each taken in the boxes' own axes as if they were
+        // orthonormal (any direction is valid; this only picks a good one).
+        // Along n the supports are exactly sum_j r_j |n.g_j| + sum_k rb_k |n.b_k|
+        // for the boxes in generator form, so only rounding needs allowances:
+        // delta_C per unit of extent for the placed axes and the dot
+        // products, 2 e_obb for the centres, 2^-20 for the sums.
+        const float cbx = pa[0] - dx, cby = pa[1] - dy, cbz = pa[2] - dz;  // B's centre
+        // u: B's point nearest to A's centre, as an offset from B's centre
+        float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float t = __builtin_fmaf(bk[3 * k], dx, __builtin_fmaf(bk[3 * k + 1], dy, bk[3 * k + 2] * dz));
+            const float tc = fminf(fmaxf(t, -rb[k]), rb[k]);
+            ux = __builtin_fmaf(tc, bk[3 * k], ux);
+            uy = __builtin_fmaf(tc, bk[3 * k + 1], uy);
+            uz = __builtin_fmaf(tc, bk[3 * k + 2], uz);
+        }
+        // A's point nearest to it (offset from A's centre)
+        const float ex = cbx + ux - pa[0], ey = cby + uy - pa[1], ez = cbz + uz - pa[2];
+        float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const float gx = pa[4 + 4 * j], gy = pa[5 + 4 * j], gz = pa[6 + 4 * j], r = pa[7 + 4 * j];
+            const float t = __builtin_fmaf(gx, ex, __builtin_fmaf(gy, ey, gz * ez));
+            const float tc = fminf(fmaxf(t, -r), r);
+            vx = __builtin_fmaf(tc, gx, vx);
+            vy = __builtin_fmaf(tc, gy, vy);
+            vz = __builtin_fmaf(tc, gz, vz);
+        }
+        // B's point nearest to that one; n points from A's point towards it
+        const float fx = pa[0] + vx - cbx, fy = pa[1] + vy - cby, fz = pa[2] + vz - cbz;
+        float wx = 0.0f, wy = 0.0f, wz = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float t = __builtin_fmaf(bk[3 * k], fx, __builtin_fmaf(bk[3 * k + 1], fy, bk[3 * k + 2] * fz));
+            const float tc = fminf(fmaxf(t, -rb[k]), rb[k]);
+            wx = __builtin_fmaf(tc, bk[3 * k], wx);
+            wy = __builtin_fmaf(tc, bk[3 * k + 1], wy);
+            wz = __builtin_fmaf(tc, bk[3 * k + 2], wz);
+        }
+        const float nx = wx - fx, ny = wy - fy, nz = wz - fz;
+        const float nn = __builtin_fmaf(nx, nx, __builtin_fmaf(ny, ny, nz * nz));
+        if (nn > 0x1p-100f) {
+            // n.(c_B - c) minus both supports along n
+            float S = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                S = __builtin_fmaf(pa[7 + 4 * j],
+                                   fabsf(__builtin_fmaf(nx, pa[4 + 4 * j], __builtin_fmaf(ny, pa[5 + 4 * j], nz * pa[6 + 4 * j]))), S);
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+                S = __builtin_fmaf(rb[k], fabsf(__builtin_fmaf(nx, bk[3 * k], __builtin_fmaf(ny, bk[3 * k + 1], nz * bk[3 * k + 2]))), S);
+            const float D = -__builtin_fmaf(nx, dx, __builtin_fmaf(ny, dy, nz * dz));
+            const float gn = __builtin_fmaf(D, 1.0f - 0x1p-20f, -S * (1.0f + 0x1p-20f)) * (1.0f / sqrtf(nn)) * (1.0f - 0x1p-20f);
+            lb = fmaxf(lb, gn - __builtin_fmaf(dC, rsumA + rsumB, 2.0f * e_obb));
+        }
     }
     *sep_out = sep;
     *lb_out = lb;
