@@ -4,7 +4,11 @@ tori, 18-DOP BVHs, branching 8, leaf size 4, 16-bit predictor-corrector codes,
 
 One step = one cbvh_collide call over the whole pose batch (per-pose setup,
 traversal, leaf tests, outputs).  Inputs are resident in HBM before timing.
-Prints one JSON line.  The uncompressed (FP32 descriptor) twin, the tiny
+The K timed steps are spread over --streams HIP streams (4 by default), each
+with its own workspace and outputs, so that several batches are in flight:
+the headline value is that whole-job rate; the same K steps one at a time
+are reported beside it ("sequential"), and every stream's answers must
+equal the one-at-a-time run's.  Prints one JSON line.  The uncompressed (FP32 descriptor) twin, the tiny
 pair-list workload and the proximity (distance) workload are timed after the
 main measurement and reported as extra fields.
 """
@@ -77,6 +81,34 @@ def time_steps(fn, steps, warmup):
     return wall, dev_ms
 
 
+def time_pipelined(fns, steps, warmup, cfg=None):
+    """K calls spread round-robin over S HIP streams, one per entry of `fns`
+    (each with its own workspace and outputs), after W untimed calls: the
+    wall clock between synchronizations.  Each call still covers the whole
+    batch; several batches are in flight at once, so one launch's tail (its
+    last long poses) overlaps the next launch's bulk.  cfg: launch knobs
+    (autotune.launch_env) for these calls."""
+    import torch
+    from paper_2012_05348_amd import autotune
+    streams = [torch.cuda.Stream() for _ in fns]
+    for s_ in streams:
+        s_.wait_stream(torch.cuda.current_stream())
+
+    def call(i):
+        with torch.cuda.stream(streams[i % len(fns)]):
+            fns[i % len(fns)]()
+
+    with autotune.launch_env(cfg):
+        for i in range(warmup):
+            call(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            call(i)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+
 def traversal_kernel_ms(cb, step, ws, calls):
     """Duration of the traversal kernel alone, measured on the device: each
     call's workspace records the device wall clock (100 MHz) when its first
@@ -91,7 +123,7 @@ def traversal_kernel_ms(cb, step, ws, calls):
     return out
 
 
-def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0, bv=None):
+def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0, bv=None, pipeline=0):
     import torch
     ma, mb = _models(cb, w, bits, dev, bv)
     P = torch.from_numpy(w.raw_poses()).to(dev)
@@ -114,12 +146,27 @@ def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0, bv=None
     progress(f"  {steps} steps, {np.mean(dev_ms):.3f} ms/call, stats {stats}")
     kern_ms = traversal_kernel_ms(cb, step, ws.buf, min(steps, 10))
     info = ma.info()
+    pipe = None
+    if pipeline:
+        # the same batch on `pipeline` streams at once; every stream's answers
+        # must equal the one-at-a-time run's
+        sets = [(cb.workspace(ma, mb, n, flags, pair_capacity, dev), torch.empty(n, dtype=torch.uint8, device=dev),
+                 torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(pipeline)]
+        fns = [lambda s_=s_: cb.cbvh_collide(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, s_[1], None, 0, None,
+                                             s_[2], s_[0].buf) for s_ in sets]
+        progress(f"  pipelined: {pipeline} streams")
+        pwall = time_pipelined(fns, steps, warmup)
+        pipe = {"streams": pipeline, "wall": pwall, "poses_per_sec": n * steps / pwall,
+                "ms_per_step": pwall / steps * 1e3,
+                "hits_equal": all(bool(torch.equal(h_, hit)) for _, h_, _ in sets),
+                "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
+        progress(f"  pipelined: {pipe['ms_per_step']:.3f} ms/step, answers equal {pipe['hits_equal']}")
     return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=status_ok, hits=int(hit.sum().item()),
-                hit=hit.cpu().numpy(),
+                hit=hit.cpu().numpy(), pipe=pipe,
                 info=info, descriptor_bytes=info["descriptor_bytes"] + mb.info()["descriptor_bytes"], kern_ms=kern_ms)
 
 
-def run_distance(cb, w, bits, dev, steps, warmup, flags=0, bv=None):
+def run_distance(cb, w, bits, dev, steps, warmup, flags=0, bv=None, pipeline=0):
     import torch
     ma, mb = _models(cb, w, bits, dev, bv)
     P = torch.from_numpy(w.raw_poses()).to(dev)
@@ -136,7 +183,24 @@ def run_distance(cb, w, bits, dev, steps, warmup, flags=0, bv=None):
     stats = cb.cbvh_stats(ws.buf)
     progress(f"  {steps} steps, {np.mean(dev_ms):.3f} ms/call, stats {stats}")
     kern_ms = traversal_kernel_ms(cb, step, ws.buf, min(steps, 10))
+    pipe = None
+    if pipeline:
+        # several batches in flight, one helper wave per CU (four, the
+        # default of a lone distance launch, hold slots the other launches
+        # need); distances must be bit-identical to the one-at-a-time run's
+        sets = [(cb.workspace(ma, mb, n, 0, 0, dev), torch.empty(n, dtype=torch.float32, device=dev),
+                 torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(pipeline)]
+        fns = [lambda s_=s_: cb.cbvh_distance(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, s_[1], s_[2],
+                                              s_[0].buf) for s_ in sets]
+        progress(f"  pipelined: {pipeline} streams, one helper per CU")
+        pwall = time_pipelined(fns, steps, warmup, cfg={"helpers_per_cu": 1})
+        pipe = {"streams": pipeline, "helpers_per_cu": 1, "wall": pwall, "poses_per_sec": n * steps / pwall,
+                "ms_per_step": pwall / steps * 1e3,
+                "distances_equal": all(bool(torch.equal(d_.view(torch.int32), d.view(torch.int32))) for _, d_, _ in sets),
+                "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
+        progress(f"  pipelined: {pipe['ms_per_step']:.3f} ms/step, answers equal {pipe['distances_equal']}")
     return dict(n=n, wall=wall, dev_ms=dev_ms, stats=stats, ok=bool((st == 0).all().item()), dist=d.cpu().numpy(),
+                pipe=pipe,
                 descriptor_bytes=ma.info()["descriptor_bytes"] + mb.info()["descriptor_bytes"], kern_ms=kern_ms)
 
 
@@ -163,6 +227,7 @@ def summarize(r, steps):
         "node_steps_per_call": s["node_steps"],
         "leaf_steps_per_call": s["leaf_steps"],
         "status_ok": r["ok"],
+        **({"pipelined": {k: v for k, v in r["pipe"].items() if k != "wall"}} if r.get("pipe") else {}),
     }
 
 
@@ -228,6 +293,16 @@ def run_batched(cb, dev, steps, warmup):
     stats = cb.cbvh_stats(ws.buf)
     ok = bool((st == 0).all().item())
     hits = hit.clone()
+    # four launches in flight on four streams
+    sets = [(cb.workspace(link, link, n, cb.EARLY_EXIT, 0, dev), torch.empty(n, dtype=torch.uint8, device=dev),
+             torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(4)]
+    fns = [lambda s_=s_: cb.cbvh_collide_batch(link.handle, link.dev, oset.handle, Pd, od, n, cb.EARLY_EXIT, s_[1], s_[2],
+                                               s_[0].buf) for s_ in sets]
+    pwall = time_pipelined(fns, steps, warmup)
+    pipelined = {"streams": len(sets), "poses_per_sec": n * steps / pwall, "ms_per_step": pwall / steps * 1e3,
+                 "hits_equal": all(bool(torch.equal(h_, hits)) for _, h_, _ in sets),
+                 "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
+    progress(f"  batched pipelined: {pipelined['ms_per_step']:.3f} ms/step")
     # the plain kernel, one launch per obstacle (poses grouped by obstacle)
     groups = []
     for k in range(w.n_obstacles):
@@ -291,6 +366,7 @@ def run_batched(cb, dev, steps, warmup):
         "obstacle_triangles": int(sum(s_.n_tris for s_ in w.obstacle_specs())),
         "poses_per_sec": n * steps / wall, "ms_per_call_median": float(np.median(dev_ms)),
         "ms_per_call_p99": float(np.percentile(dev_ms, 99)), "bv_tests_per_call": stats["bv_tests"],
+        "pipelined": pipelined,
         "status_ok": ok, "hits": int(hits.sum().item()),
         "plain_per_obstacle": {"launches": len(groups), "poses_per_sec": n * steps / pwall,
                                "ms_per_step_median": float(np.median(pdev_ms)),
@@ -503,8 +579,10 @@ def cpu_baselines_other(threads, budget_s=6.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=4,
+                    help="HIP streams the timed steps are spread over (batches in flight at once; 1 = one at a time)")
     ap.add_argument("--no-extra", action="store_true", help="skip the uncompressed twin and the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--large-obstacle-set", type=int, default=0, metavar="N",
@@ -541,9 +619,15 @@ def main():
               flush=True)
         return
     w = configs.WORKLOADS[1]
-    main_r = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT)
+    streams = max(1, args.streams)
+    main_r = run_collide(cb, w, w.bits, dev, args.steps, args.warmup, cb.EARLY_EXIT,
+                         pipeline=streams if streams > 1 else 0)
     main_s = summarize(main_r, args.steps)
-    ms_per_step = main_r["wall"] / args.steps * 1e3
+    # the headline: K steps with `streams` batches in flight (one at a time
+    # when streams = 1); the one-at-a-time run is reported beside it
+    pipe = main_r["pipe"]
+    value = pipe["poses_per_sec"] if pipe else main_s["poses_per_sec"]
+    ms_per_step = (pipe["wall"] if pipe else main_r["wall"]) / args.steps * 1e3
     # the dominant kernel's average duration, measured live on the device
     kavg_ms = float(np.mean(main_r["kern_ms"]))
     algo_bytes = main_s["algorithmic_bytes_per_call"]
@@ -566,7 +650,7 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": main_s["poses_per_sec"],
+        "value": value,
         "unit": "poses/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -581,8 +665,13 @@ def main():
             "workload": "scaled collision: noisy torus 100k tri vs noisy torus 100k tri, 18-DOP BF8 leaf 4, "
                         "16-bit predictor-corrector codes, 16384 poses, booleans with early exit",
             "poses": main_r["n"], "bv": "dop18", "branching": 8, "leaf_size": 4, "bits": 16,
-            "parallelism": "one wavefront per pose; pending node pairs handed to helper waves",
+            "parallelism": "one wavefront per pose; pending node pairs handed to helper waves; "
+                           f"{streams} batches in flight on {streams} HIP streams",
+            "streams": streams,
         },
+        "sequential": {"poses_per_sec": main_s["poses_per_sec"], "ms_per_step": main_r["wall"] / args.steps * 1e3,
+                       "ms_per_call_median": main_s["ms_per_call_median"], "ms_per_call_p99": main_s["ms_per_call_p99"]},
+        "answers_equal_across_streams": pipe["hits_equal"] if pipe else True,
         "bv_tests_per_sec": main_s["bv_tests_per_sec"],
         "compressed": main_s,
         "roofline": {
@@ -590,10 +679,15 @@ def main():
             "traffic": traffic, "kernel": "traverse_kernel<9,16,bool>", "kernel_avg_ms": kavg_ms,
             "call_avg_ms": float(np.mean(main_r["dev_ms"])), "algorithmic_bytes_per_launch": algo_bytes,
             "valu_issue": valu,
+            # the same bytes per step over the pipelined step time (several
+            # launches overlap, so this is a whole-job rate, not one kernel's)
+            "per_step_pipelined": ({"achieved": algo_bytes / (ms_per_step * 1e-3) / 1e9,
+                                    "frac": algo_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                   if pipe else None),
         },
     }
     if not args.no_extra:
-        unc = run_collide(cb, w, 0, dev, args.steps, args.warmup, cb.EARLY_EXIT)
+        unc = run_collide(cb, w, 0, dev, args.steps, args.warmup, cb.EARLY_EXIT, pipeline=streams if streams > 1 else 0)
         out["uncompressed"] = summarize(unc, args.steps)
         out["uncompressed"]["hits_equal"] = bool(np.array_equal(unc["hit"], main_r["hit"]))
         out["compression"] = {
@@ -603,6 +697,8 @@ def main():
             "bv_test_inflation": main_s["bv_tests_per_call"] / max(1, out["uncompressed"]["bv_tests_per_call"]),
             "speedup_vs_fp32": main_s["poses_per_sec"] / out["uncompressed"]["poses_per_sec"],
         }
+        if pipe and unc["pipe"]:
+            out["compression"]["speedup_vs_fp32_pipelined"] = pipe["poses_per_sec"] / unc["pipe"]["poses_per_sec"]
         # the paper's half-precision descriptors (section III.A), a third point
         f16 = run_collide(cb, w, cb.BITS_FP16, dev, args.steps, args.warmup, cb.EARLY_EXIT)
         out["fp16"] = summarize(f16, args.steps)
@@ -615,7 +711,7 @@ def main():
         out["tiny_pairs"] = summarize(tiny, 10)
         prox = {}
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
-            prox[key] = run_distance(cb, w2, bits, dev, 5, 1)
+            prox[key] = run_distance(cb, w2, bits, dev, 5, 1, pipeline=2 if key == "proximity" else 0)
             out[key] = summarize(prox[key], 5)
         # oriented boxes in the same layout (the paper's future work): the
         # scaled collision workload and the proximity workload as OBB models

@@ -34,19 +34,26 @@ from . import (DOP18, EARLY_EXIT, Model, Obstacles, cbvh_collide_batch, workspac
 
 WAVES_ENV = "CBVH_WAVES_PER_CU"
 GROUP_ENV = "CBVH_WAVES_PER_GROUP"
+HELPERS_ENV = "CBVH_MAX_HELPERS"
 CACHE_ENV = "CBVH_TUNE_CACHE"
 WHOLE_TREE = 1 << 30  # a treelet budget no model reaches: one treelet holds the whole tree
 
 
 @contextlib.contextmanager
 def launch_env(cfg):
-    """Launch knobs of a tuned configuration ({"waves_per_cu", "waves_per_group"};
-    0 or missing = the library's default) set for the duration of the block;
-    cfg None leaves the environment alone."""
+    """Launch knobs of a tuned configuration ({"waves_per_cu", "waves_per_group",
+    "helpers_per_cu"}; 0 or missing = the library's default) set for the
+    duration of the block; cfg None leaves the environment alone.
+
+    helpers_per_cu: waves per CU that stay, once the pose queue is empty, to
+    take handed-over work (the library's default: 1 for early-exit collision,
+    2 for pair lists, 4 for distances).  Waiting helpers hold their CU
+    slots, so where several launches share the GPU fewer of them leave more
+    room to the other launches' waves."""
     if cfg is None:
         yield
         return
-    saved = {k: os.environ.get(k) for k in (WAVES_ENV, GROUP_ENV)}
+    saved = {k: os.environ.get(k) for k in (WAVES_ENV, GROUP_ENV, HELPERS_ENV)}
     try:
         for key, env in (("waves_per_cu", WAVES_ENV), ("waves_per_group", GROUP_ENV)):
             v = int((cfg or {}).get(key) or 0)
@@ -54,6 +61,11 @@ def launch_env(cfg):
                 os.environ[env] = str(v)
             else:
                 os.environ.pop(env, None)
+        hp = int((cfg or {}).get("helpers_per_cu") or 0)
+        if hp:
+            os.environ[HELPERS_ENV] = str(hp * _cu_count())
+        else:
+            os.environ.pop(HELPERS_ENV, None)
         yield
     finally:
         for k, v in saved.items():
@@ -61,6 +73,12 @@ def launch_env(cfg):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+
+
+def _cu_count():
+    """Compute units of the current GPU (the library counts helpers in waves)."""
+    import torch
+    return int(torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count)
 
 
 def build_kwargs(cfg, default_branching=8):

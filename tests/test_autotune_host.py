@@ -37,3 +37,14 @@ def test_launch_env_without_a_pick_changes_nothing(monkeypatch):
     with autotune.launch_env(None):
         assert os.environ[autotune.WAVES_ENV] == "6"
     assert os.environ[autotune.WAVES_ENV] == "6"
+
+
+def test_launch_env_counts_helpers_per_cu(monkeypatch):
+    monkeypatch.setattr(autotune, "_cu_count", lambda: 256)
+    monkeypatch.setenv(autotune.HELPERS_ENV, "7")
+    with autotune.launch_env({"waves_per_group": 1, "helpers_per_cu": 2}):
+        assert os.environ[autotune.HELPERS_ENV] == "512"
+    assert os.environ[autotune.HELPERS_ENV] == "7"
+    with autotune.launch_env({"waves_per_group": 1}):
+        assert autotune.HELPERS_ENV not in os.environ
+    assert os.environ[autotune.HELPERS_ENV] == "7"
