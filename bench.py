@@ -4,7 +4,7 @@ tori, 18-DOP BVHs, branching 8, leaf size 4, 16-bit predictor-corrector codes,
 
 One step = one cbvh_collide call over the whole pose batch (per-pose setup,
 traversal, leaf tests, outputs).  Inputs are resident in HBM before timing.
-The K timed steps are spread over --streams HIP streams (4 by default), each
+The K timed steps are spread over --streams HIP streams (8 by default), each
 with its own workspace and outputs, so that several batches are in flight:
 the headline value is that whole-job rate; the same K steps one at a time
 are reported beside it ("sequential"), and every stream's answers must
@@ -25,6 +25,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# HIP maps streams onto hardware queues (4 per process by default, one of
+# them the null stream's) and runs the launches of streams that share a
+# queue one after the other; the pipelined legs below keep up to 8 launches
+# in flight, each stream on a queue of its own.  Set before HIP starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 import numpy as np  # noqa: E402
 
@@ -81,16 +87,33 @@ def time_steps(fn, steps, warmup):
     return wall, dev_ms
 
 
+# launch knobs of the pipelined collision legs: with 8 launches in flight
+# the other launches fill a launch's tail, so a few helper waves for the whole
+# GPU beat one per CU (8 streams: 0.168-0.177 ms per step with 8-64 helpers,
+# 0.21-0.22 with 256, 0.34 with 512)
+PIPE_COLLIDE_CFG = {"max_helpers": 32}
+_STREAMS = []
+
+
+def pipe_streams(n):
+    """The first n of one pool of streams made once per process (new streams
+    beyond the hardware queues would share a queue with an earlier one)."""
+    import torch
+    while len(_STREAMS) < n:
+        _STREAMS.append(torch.cuda.Stream())
+    return _STREAMS[:n]
+
+
 def time_pipelined(fns, steps, warmup, cfg=None):
     """K calls spread round-robin over S HIP streams, one per entry of `fns`
     (each with its own workspace and outputs), after W untimed calls: the
     wall clock between synchronizations.  Each call still covers the whole
     batch; several batches are in flight at once, so one launch's tail (its
-    last long poses) overlaps the next launch's bulk.  cfg: launch knobs
+    last long poses) overlaps the next launches' bulk.  cfg: launch knobs
     (autotune.launch_env) for these calls."""
     import torch
     from paper_2012_05348_amd import autotune
-    streams = [torch.cuda.Stream() for _ in fns]
+    streams = pipe_streams(len(fns))
     for s_ in streams:
         s_.wait_stream(torch.cuda.current_stream())
 
@@ -155,8 +178,8 @@ def run_collide(cb, w, bits, dev, steps, warmup, flags, pair_capacity=0, bv=None
         fns = [lambda s_=s_: cb.cbvh_collide(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, s_[1], None, 0, None,
                                              s_[2], s_[0].buf) for s_ in sets]
         progress(f"  pipelined: {pipeline} streams")
-        pwall = time_pipelined(fns, steps, warmup)
-        pipe = {"streams": pipeline, "wall": pwall, "poses_per_sec": n * steps / pwall,
+        pwall = time_pipelined(fns, steps, warmup, cfg=PIPE_COLLIDE_CFG)
+        pipe = {"streams": pipeline, **PIPE_COLLIDE_CFG, "wall": pwall, "poses_per_sec": n * steps / pwall,
                 "ms_per_step": pwall / steps * 1e3,
                 "hits_equal": all(bool(torch.equal(h_, hit)) for _, h_, _ in sets),
                 "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
@@ -293,13 +316,15 @@ def run_batched(cb, dev, steps, warmup):
     stats = cb.cbvh_stats(ws.buf)
     ok = bool((st == 0).all().item())
     hits = hit.clone()
-    # four launches in flight on four streams
+    # eight launches in flight on eight streams
     sets = [(cb.workspace(link, link, n, cb.EARLY_EXIT, 0, dev), torch.empty(n, dtype=torch.uint8, device=dev),
-             torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(4)]
+             torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(8)]
     fns = [lambda s_=s_: cb.cbvh_collide_batch(link.handle, link.dev, oset.handle, Pd, od, n, cb.EARLY_EXIT, s_[1], s_[2],
                                                s_[0].buf) for s_ in sets]
-    pwall = time_pipelined(fns, steps, warmup)
-    pipelined = {"streams": len(sets), "poses_per_sec": n * steps / pwall, "ms_per_step": pwall / steps * 1e3,
+    psteps = 6 * len(sets)  # several rounds over the streams (the first and last run partly alone)
+    pwall = time_pipelined(fns, psteps, len(sets), cfg=PIPE_COLLIDE_CFG)
+    pipelined = {"streams": len(sets), **PIPE_COLLIDE_CFG, "steps": psteps, "poses_per_sec": n * psteps / pwall,
+                 "ms_per_step": pwall / psteps * 1e3,
                  "hits_equal": all(bool(torch.equal(h_, hits)) for _, h_, _ in sets),
                  "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
     progress(f"  batched pipelined: {pipelined['ms_per_step']:.3f} ms/step")
@@ -581,7 +606,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=8)
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=8,
                     help="HIP streams the timed steps are spread over (batches in flight at once; 1 = one at a time)")
     ap.add_argument("--no-extra", action="store_true", help="skip the uncompressed twin and the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -711,8 +736,9 @@ def main():
         out["tiny_pairs"] = summarize(tiny, 10)
         prox = {}
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
-            prox[key] = run_distance(cb, w2, bits, dev, 5, 1, pipeline=2 if key == "proximity" else 0)
-            out[key] = summarize(prox[key], 5)
+            k_ = 12 if key == "proximity" else 5
+            prox[key] = run_distance(cb, w2, bits, dev, k_, 2, pipeline=2 if key == "proximity" else 0)
+            out[key] = summarize(prox[key], k_)
         # oriented boxes in the same layout (the paper's future work): the
         # scaled collision workload and the proximity workload as OBB models
         # with the same trees and code widths

@@ -42,14 +42,15 @@ WHOLE_TREE = 1 << 30  # a treelet budget no model reaches: one treelet holds the
 @contextlib.contextmanager
 def launch_env(cfg):
     """Launch knobs of a tuned configuration ({"waves_per_cu", "waves_per_group",
-    "helpers_per_cu"}; 0 or missing = the library's default) set for the
-    duration of the block; cfg None leaves the environment alone.
+    "helpers_per_cu", "max_helpers"}; 0 or missing = the library's default)
+    set for the duration of the block; cfg None leaves the environment alone.
 
     helpers_per_cu: waves per CU that stay, once the pose queue is empty, to
     take handed-over work (the library's default: 1 for early-exit collision,
-    2 for pair lists, 4 for distances).  Waiting helpers hold their CU
-    slots, so where several launches share the GPU fewer of them leave more
-    room to the other launches' waves."""
+    2 for pair lists, 4 for distances); max_helpers: the same as a count of
+    waves for the whole GPU (it wins over helpers_per_cu).  Waiting helpers
+    hold their CU slots, so where several launches share the GPU fewer of
+    them leave more room to the other launches' waves."""
     if cfg is None:
         yield
         return
@@ -62,7 +63,10 @@ def launch_env(cfg):
             else:
                 os.environ.pop(env, None)
         hp = int((cfg or {}).get("helpers_per_cu") or 0)
-        if hp:
+        mh = int((cfg or {}).get("max_helpers") or 0)
+        if mh:
+            os.environ[HELPERS_ENV] = str(mh)
+        elif hp:
             os.environ[HELPERS_ENV] = str(hp * _cu_count())
         else:
             os.environ.pop(HELPERS_ENV, None)

@@ -47,4 +47,6 @@ def test_launch_env_counts_helpers_per_cu(monkeypatch):
     assert os.environ[autotune.HELPERS_ENV] == "7"
     with autotune.launch_env({"waves_per_group": 1}):
         assert autotune.HELPERS_ENV not in os.environ
+    with autotune.launch_env({"helpers_per_cu": 2, "max_helpers": 32}):
+        assert os.environ[autotune.HELPERS_ENV] == "32"
     assert os.environ[autotune.HELPERS_ENV] == "7"
