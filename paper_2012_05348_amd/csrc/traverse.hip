@@ -735,10 +735,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
         }
         if (!poses_left) {
             if (!can_donate) break;
-            // the first waves of the workgroups with the lowest indices
-            // (spread over the XCDs and CUs by the dispatcher) stay as
-            // helpers; the others exit
-            if (blockIdx.x >= q.max_helpers || wave_in_group != 0) break;
+            // the waves of the workgroups with the lowest indices (spread
+            // over the XCDs and CUs by the dispatcher) stay as helpers, all
+            // waves of a workgroup together: a workgroup's LDS is held
+            // until its last wave exits, so a lone helper wave would pin
+            // its partners' LDS too; the others exit
+            if (wave_id >= q.max_helpers) break;
             uint32_t slot = 0;
             if (lane == 0) slot = rmw_add(&hdr->q_head, 1u);
             slot = uni(slot);

@@ -147,9 +147,7 @@ class Server:
         # which the library takes for distance queries otherwise, made loaded
         # latencies several times worse and the saturation rate lower; the
         # four helpers per CU of a lone distance launch, which wait holding
-        # their CU slots, cost 2-7 % of the saturation rate here (and three
-        # distance launches in flight at once, each with four, ran 17 times
-        # slower than with one)
+        # their CU slots, cost 2-7 % of the saturation rate here
         self.launch_cfg = {"waves_per_group": 1, "helpers_per_cu": 1} if launch_cfg is None else launch_cfg
         # the largest launch that lets every slot's workspace fit the budget
         if max_poses is None:
