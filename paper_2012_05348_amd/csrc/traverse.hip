@@ -57,9 +57,20 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// square root for the BV bounds: the hardware instruction (within 1 ulp),
+// whose error the bounds' 2^-20 relative factors cover, instead of the
+// correctly rounded expansion (about 15 instructions)
+__device__ __forceinline__ float bound_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ uint32_t lane_of(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
-// a float not below the exact sum a + b
-__device__ __forceinline__ float add_up(float a, float b) { return nextafterf(a + b, INFINITY); }
+// a float not below the exact sum a + b, for a + b >= 0 (distances plus
+// error allowances): the sum rounded to nearest, then the next float up
+// (the same as nextafterf(a + b, INFINITY) there, in two instructions
+// instead of a library call; an infinite sum is kept)
+__device__ __forceinline__ float add_up(float a, float b)
+{
+    const float x = a + b;
+    return x < INFINITY ? __uint_as_float(__float_as_uint(x) + 1u) : x;
+}
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -662,7 +673,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
             V3<float> cc = {0.5f * (b[0] + b[1]), 0.5f * (b[2] + b[3]), 0.5f * (b[4] + b[5])};
             float hx = 0.5f * (b[1] - b[0]), hy = 0.5f * (b[3] - b[2]), hz = 0.5f * (b[5] - b[4]);
             // the map stretches lengths by at most 1 + 1.5 rot_eps
-            float r = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f + 2.0f * rot_eps);
+            float r = bound_sqrt(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f + 2.0f * rot_eps);
             V3<float> cw = xform_f32(P, cc);
             tsph[2 * c] = make_float4(cw.x, cw.y, cw.z, r);
             tsph[2 * c + 1] = make_float4(hx, hy, hz, hx + hy + hz);  // A-frame half extents
@@ -1043,10 +1054,10 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                         const float4 sa = tsph[2 * ia];
                         const float cx = 0.5f * (bB[0] + bB[1]), cy = 0.5f * (bB[2] + bB[3]), cz = 0.5f * (bB[4] + bB[5]);
                         const float hx = 0.5f * (bB[1] - bB[0]), hy = 0.5f * (bB[3] - bB[2]), hz = 0.5f * (bB[5] - bB[4]);
-                        const float rb = sqrtf(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
+                        const float rb = bound_sqrt(hx * hx + hy * hy + hz * hz) * (1.0f + 0x1p-20f);
                         const float dx = sa.x - cx, dy = sa.y - cy, dz = sa.z - cz;
                         const float4 ez = pz[3];
-                        const float gs = sqrtf(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - ez.y;
+                        const float gs = bound_sqrt(dx * dx + dy * dy + dz * dz) * (1.0f - 0x1p-20f) - sa.w - rb - ez.y;
                         // third lower bound: the gap along one well-chosen direction
                         // (gaps along A's own axes, tried beside it, pruned no more)
                         const Pose P = pose_of();
@@ -1227,7 +1238,7 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                                 const float x = fmaxf(ga, 0.0f), y = fmaxf(gb, 0.0f), z = fmaxf(gc, 0.0f);
                                 g2 = __builtin_fmaf(x, x, __builtin_fmaf(y, y, z * z));
                             }
-                            keep = sqrtf(g2) * (1.0f - 0x1p-20f) - e_abs <= tau;
+                            keep = bound_sqrt(g2) * (1.0f - 0x1p-20f) - e_abs <= tau;
                         }
                         const uint64_t mk = __ballot(keep);
                         if (keep) tq[n_full + mbcnt(mk)] = make_uint2(tA, tB);
