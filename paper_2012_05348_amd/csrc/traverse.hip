@@ -89,14 +89,20 @@ __device__ __forceinline__ uint32_t dpp_or(uint32_t identity, uint32_t v)
 // wave's minimum.  All register-to-register (no LDS round trips).
 __device__ __forceinline__ float wave_min(float v)
 {
-    const uint32_t inf = 0x7F800000u;
-    v = fminf(v, __uint_as_float(dpp_or<0x111, 0xF>(inf, __float_as_uint(v))));
-    v = fminf(v, __uint_as_float(dpp_or<0x112, 0xF>(inf, __float_as_uint(v))));
-    v = fminf(v, __uint_as_float(dpp_or<0x114, 0xF>(inf, __float_as_uint(v))));
-    v = fminf(v, __uint_as_float(dpp_or<0x118, 0xF>(inf, __float_as_uint(v))));
-    v = fminf(v, __uint_as_float(dpp_or<0x142, 0xA>(inf, __float_as_uint(v))));
-    v = fminf(v, __uint_as_float(dpp_or<0x143, 0xC>(inf, __float_as_uint(v))));
-    return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 63));
+    // on keys that order as the floats do (sign bit flipped for positive
+    // values, every bit for negative ones), so that each step is an integer
+    // minimum the DPP move folds into
+    const uint32_t b = __float_as_uint(v);
+    uint32_t k = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+    const uint32_t top = 0xFFFFFFFFu;
+    k = min(k, dpp_or<0x111, 0xF>(top, k));
+    k = min(k, dpp_or<0x112, 0xF>(top, k));
+    k = min(k, dpp_or<0x114, 0xF>(top, k));
+    k = min(k, dpp_or<0x118, 0xF>(top, k));
+    k = min(k, dpp_or<0x142, 0xA>(top, k));
+    k = min(k, dpp_or<0x143, 0xC>(top, k));
+    k = __builtin_amdgcn_readlane(k, 63);
+    return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
 }
 // DPP row shifts (within each row of 16 lanes; 0 where there is no source lane)
 template <int N>
