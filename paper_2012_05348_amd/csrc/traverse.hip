@@ -1557,9 +1557,12 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     load_rec(prec, pb);
                     decode_child<K, BITS, OBB>(M, my_topo, nw, pb, my_b);
                 }
-            }
-            wave_sync();
-            if (dec) {
+                // the new frame may overwrite records that other decoding
+                // lanes read above: the wave's LDS accesses run in program
+                // order, so only the compiler must keep the stores below
+                // the reads (one block, so the decoded bounds need no copies
+                // for the lanes that decode nothing)
+                wave_sync();
                 store_rec(new_base + lane, my_b, my_topo);
                 if (sideA) prep_A(lane, my_b, my_topo);
             }
