@@ -993,11 +993,13 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                     // (culled entries of distance queries have no tasks and are
                     // passed over)
                     uint32_t w = lane_of(f_meta, 0);
+                    if (f_ns > 1) {
 #pragma unroll
-                    for (int s = 1; s < PMAX; s++) {
-                        if ((uint32_t)s < f_ns) {
-                            const uint32_t ws = lane_of(f_meta, s);
-                            if ((ws >> 24) <= lane) w = ws;
+                        for (int s = 1; s < PMAX; s++) {
+                            if ((uint32_t)s < f_ns) {
+                                const uint32_t ws = lane_of(f_meta, s);
+                                if ((ws >> 24) <= lane) w = ws;
+                            }
                         }
                     }
                     const uint32_t aoff = w & 0xFFu, boff = (w >> 8) & 0xFFu, nb = (w >> 16) & 0xFFu;
@@ -1513,13 +1515,14 @@ void traverse_kernel(QueryArgs q, StackLimits lim)
                 g_pB = uni(my_tB);
             } else {
                 uint32_t e = 0;
+                const uint32_t sh = sideA ? 0u : 8u;  // A's or B's record count in the packed prefix
 #pragma unroll
                 // (the last popped entry's run ends past every record of its
                 // side, so only the first n_pop - 1 ends are compared)
                 for (int s = 0; s < PMAX - 1; s++) {
                     if ((uint32_t)s + 1u >= n_pop) break;
                     const uint32_t w = lane_of(pk, s);
-                    const uint32_t end = sideA ? (w & 0xFFu) : ((w >> 8) & 0xFFu);
+                    const uint32_t end = (w >> sh) & 0xFFu;
                     if (end <= r) {
                         e = (uint32_t)s + 1u;
                         off = end;
