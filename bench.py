@@ -736,7 +736,7 @@ def main():
         out["tiny_pairs"] = summarize(tiny, 10)
         prox = {}
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
-            k_ = 12 if key == "proximity" else 5
+            k_ = 20 if key == "proximity" else 5
             prox[key] = run_distance(cb, w2, bits, dev, k_, 2, pipeline=2 if key == "proximity" else 0)
             out[key] = summarize(prox[key], k_)
         # oriented boxes in the same layout (the paper's future work): the
