@@ -90,8 +90,10 @@ def time_steps(fn, steps, warmup):
 # launch knobs of the pipelined collision legs: with 8 launches in flight
 # the other launches fill a launch's tail, so a few helper waves for the whole
 # GPU beat one per CU (8 streams: 0.168-0.177 ms per step with 8-64 helpers,
-# 0.21-0.22 with 256, 0.34 with 512)
-PIPE_COLLIDE_CFG = {"max_helpers": 32}
+# 0.21-0.22 with 256, 0.34 with 512), and each launch taking half of a CU's
+# wave slots lets two run side by side (32 helpers: 0.151-0.153 ms per step
+# with 6 waves per CU, 0.163-0.164 with 8 or 10, 0.173 with all 12)
+PIPE_COLLIDE_CFG = {"max_helpers": 32, "waves_per_cu": 6}
 _STREAMS = []
 
 

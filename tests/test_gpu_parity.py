@@ -510,8 +510,9 @@ def test_concurrent_launches_on_several_streams_neither_wait_nor_change_answers(
 
 def test_eight_collision_launches_in_flight_with_few_helpers_keep_answers():
     """The bench's pipelined setting: eight scaled collision launches in
-    flight on eight streams with 32 helper waves for the whole GPU; every
-    launch's booleans equal the lone launch's, with no wait-limit timeout."""
+    flight on eight streams, each with 6 waves per CU and 32 helper waves for
+    the whole GPU; every launch's booleans equal the lone launch's, with no
+    wait-limit timeout."""
     from paper_2012_05348_amd import autotune
     wc = configs.WORKLOADS[1]
     P = torch.from_numpy(wc.raw_poses()).to(DEV)
@@ -522,7 +523,7 @@ def test_eight_collision_launches_in_flight_with_few_helpers_keep_answers():
     streams = [torch.cuda.Stream() for _ in range(8)]
     sets = [(cb.workspace(mc[0], mc[1], n, cb.EARLY_EXIT, 0, DEV), torch.empty(n, dtype=torch.uint8, device=DEV),
              torch.empty(n, dtype=torch.uint8, device=DEV)) for _ in streams]
-    with autotune.launch_env({"max_helpers": 32}):
+    with autotune.launch_env({"max_helpers": 32, "waves_per_cu": 6}):
         for r in range(3):
             for s, (ws, out, st) in zip(streams, sets):
                 cb.cbvh_collide(mc[0].handle, mc[0].dev, mc[1].handle, mc[1].dev, P, n, cb.EARLY_EXIT, out, None, 0,
