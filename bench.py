@@ -94,6 +94,11 @@ def time_steps(fn, steps, warmup):
 # wave slots lets two run side by side (32 helpers: 0.151-0.153 ms per step
 # with 6 waves per CU, 0.163-0.164 with 8 or 10, 0.173 with all 12)
 PIPE_COLLIDE_CFG = {"max_helpers": 32, "waves_per_cu": 6}
+# and of the pipelined distance leg: one helper per CU (the four of a lone
+# distance launch hold slots the other launches need) and 6 of a CU's 10
+# wave slots per launch (4 streams: 3.73 ms per batch, against 3.83 with 8
+# waves per CU and 3.94 with 10 on 2 streams)
+PIPE_DIST_CFG = {"helpers_per_cu": 1, "waves_per_cu": 6}
 _STREAMS = []
 
 
@@ -210,16 +215,15 @@ def run_distance(cb, w, bits, dev, steps, warmup, flags=0, bv=None, pipeline=0):
     kern_ms = traversal_kernel_ms(cb, step, ws.buf, min(steps, 10))
     pipe = None
     if pipeline:
-        # several batches in flight, one helper wave per CU (four, the
-        # default of a lone distance launch, hold slots the other launches
-        # need); distances must be bit-identical to the one-at-a-time run's
+        # several batches in flight (PIPE_DIST_CFG); distances must be
+        # bit-identical to the one-at-a-time run's
         sets = [(cb.workspace(ma, mb, n, 0, 0, dev), torch.empty(n, dtype=torch.float32, device=dev),
                  torch.empty(n, dtype=torch.uint8, device=dev)) for _ in range(pipeline)]
         fns = [lambda s_=s_: cb.cbvh_distance(ma.handle, ma.dev, mb.handle, mb.dev, P, n, flags, s_[1], s_[2],
                                               s_[0].buf) for s_ in sets]
-        progress(f"  pipelined: {pipeline} streams, one helper per CU")
-        pwall = time_pipelined(fns, steps, warmup, cfg={"helpers_per_cu": 1})
-        pipe = {"streams": pipeline, "helpers_per_cu": 1, "wall": pwall, "poses_per_sec": n * steps / pwall,
+        progress(f"  pipelined: {pipeline} streams")
+        pwall = time_pipelined(fns, steps, warmup, cfg=PIPE_DIST_CFG)
+        pipe = {"streams": pipeline, **PIPE_DIST_CFG, "wall": pwall, "poses_per_sec": n * steps / pwall,
                 "ms_per_step": pwall / steps * 1e3,
                 "distances_equal": all(bool(torch.equal(d_.view(torch.int32), d.view(torch.int32))) for _, d_, _ in sets),
                 "status_ok": all(bool((st_ == 0).all().item()) for _, _, st_ in sets)}
@@ -739,7 +743,7 @@ def main():
         prox = {}
         for bits, key in ((w2.bits, "proximity"), (0, "proximity_fp32"), (cb.BITS_FP16, "proximity_fp16")):
             k_ = 20 if key == "proximity" else 5
-            prox[key] = run_distance(cb, w2, bits, dev, k_, 2, pipeline=2 if key == "proximity" else 0)
+            prox[key] = run_distance(cb, w2, bits, dev, k_, 2, pipeline=4 if key == "proximity" else 0)
             out[key] = summarize(prox[key], k_)
         # oriented boxes in the same layout (the paper's future work): the
         # scaled collision workload and the proximity workload as OBB models
