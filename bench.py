@@ -129,7 +129,9 @@ def time_pipelined(fns, steps, warmup, cfg=None):
             fns[i % len(fns)]()
 
     with autotune.launch_env(cfg):
-        for i in range(warmup):
+        # (every stream runs at least one untimed call: a stream's first
+        # launch also sets up its hardware queue)
+        for i in range(max(warmup, len(fns))):
             call(i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
